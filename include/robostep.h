@@ -1,0 +1,299 @@
+/*
+ * robostep.h -- C ABI of the MI355X (gfx950) batched Robotarium environment
+ * step: single-integrator commands mapped to unicycle commands through a
+ * projection point, filtered by a barrier-certificate QP, integrated with a
+ * fixed dt, with observations, rewards and resets, across many environments
+ * at once.
+ *
+ * The method is JaxRobotarium's simulator (arXiv 2505.06771): Sec. 4.1
+ * "Design" (unicycle GRITSBot model, single-integrator/unicycle controllers,
+ * control barrier certificates solving a QP, vectorised over environments) and
+ * the Navigation (MAPF) scenario of the appendix (observation of own position
+ * and goal vector, reward -1 x distance to goal). The paper gives no formulas;
+ * the definitions each call implements are stated on the call.
+ *
+ * Conventions shared by every call:
+ *  - All array arguments are DEVICE pointers unless marked "host". They are
+ *    owned by the caller, must stay valid until the stream work completes and
+ *    must be aligned to their element size. Float arrays hold float (RS_F32)
+ *    or double (RS_F64) according to rs_params.dtype, unless typed here.
+ *  - Robot-indexed arrays are structure-of-arrays with robot r of environment
+ *    e at index e*N + r (uniform batches) or robot_offset[e] + r (mixed).
+ *  - `stream` is a hipStream_t (NULL = the null stream). Every call only
+ *    enqueues work; results are valid once the stream has reached it.
+ *  - Argument errors are detected before anything is enqueued and return
+ *    RS_ERR_INVALID_ARG / RS_ERR_UNSUPPORTED with a message in rs_last_error().
+ *    Launch failures return RS_ERR_DEVICE. Nothing aborts or throws across the
+ *    ABI. An rs_ctx is not thread-safe: use one per host thread.
+ *  - Per-environment infeasibility of the QP is data, not an error: the
+ *    `infeasible` flag is set and the command falls back to the per-coordinate
+ *    clip of the nominal command to its bounds (midpoint where they cross).
+ */
+#ifndef ROBOSTEP_H
+#define ROBOSTEP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RS_OK = 0,
+  RS_ERR_INVALID_ARG = 1,
+  RS_ERR_UNSUPPORTED = 2,
+  RS_ERR_OUT_OF_MEMORY = 3,
+  RS_ERR_DEVICE = 4,
+  RS_ERR_BUDGET = 5,
+  RS_ERR_NOT_FOUND = 6
+} rs_status;
+
+enum { RS_F32 = 0, RS_F64 = 1 };
+enum { RS_CTRL_DISCRETE = 0, RS_CTRL_GOTO = 1 };
+enum { RS_MAX_ROBOTS = 16 };
+
+/* Simulation constants (host struct, copied at each call). Units: m, s, rad.
+ * Defaults (rs_params_default): arena [-1.6,1.6]x[-1,1], dt 0.033, projection
+ * distance 0.05, barrier gain 100 with a cubic class-K term, safety radius
+ * 0.17, wall gain factor 0.4, |u_k| <= 0.2 and |u_nom| <= 0.2, discrete move
+ * speed 0.2, go-to-goal gain 1, wheel radius 0.016 and axle 0.105 (wheel
+ * speed limit v_max / R), goal radius 0.05, 500-step episodes, reset lattice
+ * 1e-4 m inside a 0.2 m margin with 0.3 m separation. */
+typedef struct {
+  double x_min, x_max, y_min, y_max;
+  double dt;
+  double proj_dist;
+  double barrier_gain;
+  double safety_radius;
+  double boundary_gain_factor;
+  double v_max;
+  double action_speed;
+  double kp;
+  double wheel_radius; /* 0 disables wheel saturation */
+  double base_length;
+  double goal_radius;  /* <= 0 disables the all-at-goal termination */
+  double reset_margin;
+  double min_sep;
+  double grid;
+  int32_t max_steps;   /* <= 0 disables the time limit */
+  int32_t controller;  /* RS_CTRL_DISCRETE or RS_CTRL_GOTO */
+  int32_t dtype;       /* RS_F32 or RS_F64 */
+  int32_t qp_max_iters; /* cap on active-set iterations per env; 0 = 8N+32 */
+  uint64_t seed;       /* key of the counter-based stream */
+} rs_params;
+
+/* Environment batch: device structure-of-arrays views, caller-owned. */
+typedef struct {
+  int32_t num_envs;
+  int32_t robots;              /* N (2..16) for uniform batches */
+  void *x, *y, *theta;         /* [E*N] pose */
+  void *goal_x, *goal_y;       /* [E*N] goal */
+  int32_t *step;               /* [E] steps since the last reset */
+  int32_t *episode;            /* [E] episode index (keys the reset sampler) */
+  uint64_t env_id_base;        /* global id of env 0 (keys the stream) */
+} rs_batch;
+
+/* Policy of the fused rollout: in_dim = 2N+4 -> 64 -> 64 -> 5, ReLU.
+ * w1 [in_dim][64], w2 [64][64], w3 [64][5] bfloat16 (uint16 bit patterns,
+ * row-major [in][out]); b1 [64], b2 [64], b3 [5] float. Device pointers. */
+typedef struct {
+  const uint16_t *w1, *w2, *w3;
+  const float *b1, *b2, *b3;
+  int32_t in_dim;
+} rs_policy;
+
+typedef struct rs_ctx rs_ctx;
+typedef struct rs_plan rs_plan;
+
+void rs_params_default(rs_params *p);
+const char *rs_status_string(rs_status s);
+/* Message of the last failed call on this host thread ("" if none). */
+const char *rs_last_error(void);
+
+/* Create a context on HIP device `device` (workspace, schedule table, graph
+ * cache). */
+rs_status rs_create(int device, rs_ctx **out);
+rs_status rs_destroy(rs_ctx *ctx);
+
+/* ---------------------------------------------------------------------------
+ * env_reset -- reset sampler (start poses uniform with a minimum separation,
+ * goals uniform, headings uniform; the single-env navigation configuration of
+ * the paper's Sec. 4.2 evaluation scenario and the Navigation appendix).
+ * For every env e with mask[e] != 0 (mask NULL = all): positions and goals are
+ * drawn on the integer lattice of pitch `grid` inside the arena shrunk by
+ * `reset_margin`; robot i keeps the first of up to 64 draws (Philox4x32-10,
+ * key = seed, counter = (env_id, episode[e], purpose<<24 | i, attempt),
+ * purpose 2 for poses and 3 for goals) whose squared lattice distance to every
+ * robot < i is >= round(min_sep/grid)^2, else the first point of a row-major
+ * scan of every 500th lattice point that is; headings are -pi + 2 pi u with u
+ * the 24-bit uniform of word i&3 of block (env_id, episode, 4<<24 | i>>2, 0).
+ * step[e] is set to 0; episode[e] is left as given. obs (may be NULL) gets the
+ * observation [E*N][2N+4] of the reset envs (others untouched).
+ * ------------------------------------------------------------------------- */
+rs_status env_reset(rs_ctx *ctx, const rs_params *p, const rs_batch *b, const uint8_t *mask,
+                    void *obs, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * env_step -- one step of every env of the batch (Sec. 4.1 "Design"):
+ *  1. nominal single-integrator command at the projection point
+ *     p_i = (x_i + l cos th_i, y_i + l sin th_i): discrete move
+ *     action_speed * {0, +x, -x, +y, -y}[a_i] (actions NULL: a_i =
+ *     floor(5 r / 2^32), r = word i&3 of block (env_id, t_global, i>>2, 0)),
+ *     or kp (g_i - p_i) for RS_CTRL_GOTO; magnitude clipped to v_max;
+ *  2. barrier certificate: u = argmin |u - u_nom|^2 subject to, for i<j,
+ *     -2 D.u_i + 2 D.u_j <= gamma (|D|^2 - r_s^2)^3 with D = p_i - p_j, and
+ *     per coordinate lo <= u <= hi where hi_x = min(v_max, c_b gamma
+ *     (x_max - r_s/2 - p_x)^3), lo_x = max(-v_max, -c_b gamma
+ *     (p_x - x_min - r_s/2)^3) (same in y), solved exactly;
+ *  3. v = cos th u_x + sin th u_y, w = (-sin th u_x + cos th u_y)/l, wheel
+ *     speeds (v +- w L/2)/R clipped to +-v_max/R and mapped back;
+ *  4. Euler: x += dt v cos th, y += dt v sin th, th += dt w, wrapped to
+ *     [-pi, pi];
+ *  5. step += 1; reward = -sum_i |(x_i, y_i) - g_i|; done = (all distances <
+ *     goal_radius) or step >= max_steps; done envs are reset (episode += 1);
+ *  6. obs [E*N][2N+4] of the post-step (post-reset) state, per robot: x, y,
+ *     cos th, sin th, (x_j - x_i, y_j - y_i) for j != i ascending, g_i - (x,y).
+ * actions: [E*N] uint8 in 0..4 or NULL. reward [E] (float/double), done [E],
+ * max_violation [E] float (NULL ok: largest normalised row/bound violation of
+ * the command), infeasible [E] (NULL ok). obs/reward/done may be NULL.
+ * ------------------------------------------------------------------------- */
+rs_status env_step(rs_ctx *ctx, const rs_params *p, const rs_batch *b, const uint8_t *actions,
+                   int64_t t_global, void *obs, void *reward, uint8_t *done, float *max_violation,
+                   uint8_t *infeasible, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * barrier_certificate -- steps 1 (pre-clip) and 2 of env_step alone, for
+ * E environments of N robots: given projection points (px, py) and nominal
+ * commands (ux_nom, uy_nom) [E*N], writes the exact minimiser (ux, uy) [E*N].
+ * lambda (may be NULL): [E][N(N-1)/2] multipliers of the pairwise rows (pairs
+ * i<j in lexicographic order) for the objective |u - u_nom|^2; not unique
+ * under degeneracy. max_violation [E] float and infeasible [E] may be NULL.
+ * ------------------------------------------------------------------------- */
+rs_status barrier_certificate(rs_ctx *ctx, const rs_params *p, int32_t num_envs, int32_t robots,
+                              const void *px, const void *py, const void *ux_nom,
+                              const void *uy_nom, void *ux, void *uy, void *lambda,
+                              float *max_violation, uint8_t *infeasible, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * rollout -- `horizon` fused policy steps in one persistent launch (FP32 state,
+ * RS_CTRL_DISCRETE). For t = 0..H-1: obs_t of the current state; logits =
+ * MLP(bf16(obs_t)) with bf16 weights and activations and FP32 accumulation;
+ * a_t drawn by inverse CDF of softmax(logits) with the 24-bit uniform of word
+ * i&3 of block (env_id, t_global0 + t, 1<<24 | i>>2, 0); then env_step with a_t
+ * (stream time t_global0 + t). Outputs: obs [H][E*N][2N+4] float (may be NULL),
+ * actions [H][E*N] uint8, reward [H][E] float, done [H][E] uint8. The batch
+ * state is left at the post-rollout state. Requires 2N+4 <= 32.
+ * The launch is captured once per (shape, pointers) in a hipGraph and replayed.
+ * ------------------------------------------------------------------------- */
+rs_status rollout(rs_ctx *ctx, const rs_params *p, const rs_batch *b, const rs_policy *policy,
+                  int32_t horizon, int64_t t_global0, float *obs, uint8_t *actions,
+                  float *reward, uint8_t *done, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Mixed-size batches (environments with different robot counts in one launch).
+ * A plan holds the schedule: envs grouped by robot count into wavefront tiles
+ * (envs per wavefront chosen per robot count by the autotuner or `schedule`).
+ * robots_per_env is a HOST array [E] of counts in 2..16; the robot arrays of a
+ * mixed batch are laid out env after env (robot_offset = prefix sum).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t block_threads;     /* 64..1024, multiple of 64; 0 = 256 */
+  int32_t lanes_per_env[17]; /* indexed by N: power of two >= N, <= 16; 0 = smallest */
+  int32_t qp_iters[17];      /* indexed by N: active-set iteration cap; 0 = 8N+32 */
+} rs_schedule;
+
+rs_status rs_plan_create(rs_ctx *ctx, int32_t num_envs, const int32_t *robots_per_env,
+                         const rs_schedule *schedule, rs_plan **out);
+rs_status rs_plan_destroy(rs_plan *plan);
+/* Total robots of the plan and the device prefix-sum array [E+1]. */
+int64_t rs_plan_total_robots(const rs_plan *plan);
+const int32_t *rs_plan_robot_offset(const rs_plan *plan);
+
+/* env_reset for a mixed batch (FP32): b->robots is ignored; arrays use the
+ * plan's robot offsets; reset definition as env_reset. */
+rs_status env_reset_mixed(rs_ctx *ctx, const rs_params *p, const rs_plan *plan,
+                          const rs_batch *b, const uint8_t *mask, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * env_run -- `steps` consecutive env_step calls with drawn actions for a mixed
+ * batch in ONE persistent launch (FP32). Env e runs
+ * steps_per_env ? min(steps, steps_per_env[e]) : steps steps, with stream time
+ * t_start[e] + k (t_start NULL: t_global0 + k) at its k-th step. Outputs (each
+ * may be NULL): reward_out/done_out [steps][E] (rows past an env's own count
+ * untouched), reward_sum [E] (accumulated: += sum of the env's rewards),
+ * obs_final: observation of the final state, env e's block of N_e x (2N_e+4)
+ * floats starting at rs_plan_obs_offset(plan, e). Results per env do not
+ * depend on the other envs in the batch or on the schedule (as long as the
+ * iteration cap is not reached).
+ * ------------------------------------------------------------------------- */
+rs_status env_run(rs_ctx *ctx, const rs_params *p, const rs_plan *plan, const rs_batch *b,
+                  int32_t steps, const int64_t *t_start, int64_t t_global0,
+                  const int32_t *steps_per_env, float *reward_out, uint8_t *done_out,
+                  float *reward_sum, float *obs_final, void *stream);
+/* Offset of env e's observation block in obs_final (host query). */
+int64_t rs_plan_obs_offset(const rs_plan *plan, int32_t env);
+
+/* ---------------------------------------------------------------------------
+ * Autotuner: for each robot count N in `robots` (host [count]), run env_run on
+ * `envs` synthetic envs (half drawn by the reset sampler, half packed in a
+ * tight cluster so the certificate binds) for `steps` steps under each
+ * candidate schedule: lanes per env (envs per wavefront = 64 / lanes) in
+ * {smallest power of two >= N, twice that <= 16}, block size in {64, 128,
+ * 256}, active-set iteration cap in {2N+4, 4N+8, 8N+32}. A candidate is
+ * admissible when every final position matches the widest-cap reference
+ * within steps * dt * tol (tol in m/s); the fastest admissible one is kept
+ * per N in the context's schedule table (used by plans created afterwards
+ * with schedule NULL) and returned in `out` (may be NULL).
+ * ------------------------------------------------------------------------- */
+rs_status rs_autotune(rs_ctx *ctx, const rs_params *p, const int32_t *robots, int32_t count,
+                      int32_t envs, int32_t steps, double tol, rs_schedule *out);
+rs_status rs_get_schedule(rs_ctx *ctx, rs_schedule *out);
+
+/* ---------------------------------------------------------------------------
+ * Serving loop (continuous batching of rollout requests).
+ * A request is (envs, robots, horizon, seed): envs environments of `robots`
+ * robots reset from the sampler (env ids = the request's id << 20 | e, episode
+ * 0) and stepped `horizon` times with drawn actions; its result is the final
+ * pose of every robot and the summed reward of every env. The server admits
+ * queued requests in arrival order while their device bytes fit in the HBM
+ * budget, keeps all admitted state device-resident, and advances every
+ * admitted env `tick_steps` steps per tick with one persistent env_run launch
+ * over all of them, so requests that arrive while others run join at the next
+ * tick. Results of a request do not depend on what else is admitted.
+ * ------------------------------------------------------------------------- */
+typedef struct rs_server rs_server;
+typedef struct {
+  int64_t id;
+  int32_t envs, robots, horizon;
+  double submit_time, admit_time, finish_time; /* seconds, steady clock */
+} rs_request_info;
+
+rs_status rs_server_create(rs_ctx *ctx, const rs_params *p, int64_t hbm_budget_bytes,
+                           int32_t tick_steps, rs_server **out);
+rs_status rs_server_destroy(rs_server *s);
+/* Device bytes a request needs while admitted. */
+int64_t rs_request_bytes(int32_t envs, int32_t robots);
+/* Queue a request; returns RS_ERR_BUDGET if it can never fit. */
+rs_status rs_server_submit(rs_server *s, int64_t id, int32_t envs, int32_t robots,
+                           int32_t horizon);
+/* Run one tick: admit, launch, retire finished requests. *busy = 1 while any
+ * request is queued or running. */
+rs_status rs_server_tick(rs_server *s, int32_t *busy);
+/* Pop one finished request: copies its result to host arrays
+ * final_xy [envs*robots*2] (x, y interleaved) and reward_sum [envs] (either
+ * may be NULL). Returns RS_ERR_NOT_FOUND when none is finished. */
+rs_status rs_server_poll(rs_server *s, rs_request_info *info, float *final_xy,
+                         float *reward_sum);
+typedef struct {
+  int64_t submitted, admitted, finished, ticks;
+  int64_t robot_steps;       /* total robot-steps executed */
+  int64_t bytes_in_use, peak_bytes;
+  int32_t queued, running;
+} rs_server_stats;
+rs_status rs_server_stats_get(rs_server *s, rs_server_stats *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,479 @@
+// rs_mixed.hip -- persistent env_run kernel over mixed robot counts, plans,
+// env_reset_mixed, env_run and the schedule autotuner.
+//
+// A plan sorts environments by lanes-per-env G (then by N) and cuts them into
+// tiles of at most 64/G environments; each wavefront takes one tile and runs
+// every step of the launch for it with the state in registers, so a launch
+// covers envs of all sizes at once. G only changes how many envs share a
+// wavefront: the arithmetic of an env is the same for every G (padding lanes
+// add exact zeros), so results do not depend on the schedule.
+#include "rs_run.hpp"
+#include "rs_step.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <numeric>
+
+namespace rs {
+
+template <int G> constexpr int qp_bytes_per_wave() {
+  return (64 / G) * (int)sizeof(QPScratch<float, G>);
+}
+constexpr int kMaxWaveLds =
+    std::max(std::max(qp_bytes_per_wave<2>(), qp_bytes_per_wave<4>()),
+             std::max(qp_bytes_per_wave<8>(), qp_bytes_per_wave<16>()));
+
+template <int G>
+__device__ void run_tile(const RunArgs &A, char *wave_lds, int lane, int first, int count) {
+  QPScratch<float, G> *sh = reinterpret_cast<QPScratch<float, G> *>(wave_lds) + lane / G;
+  const int i = lane & (G - 1);
+  const int grp = lane / G;
+  if (grp >= count) return;  // whole group
+  const int e = A.items[first + grp];
+  const int N = A.nrob[e];
+  const bool on = i < N;
+  const size_t r = (size_t)A.offset[e] + (on ? i : 0);
+  const uint32_t env_id = A.env_ids ? A.env_ids[e] : A.env_base + (uint32_t)e;
+  SimConst<float> C = A.C;
+  C.qp_cap = A.qp_iters[N];
+
+  float x = 0.f, y = 0.f, th = 0.f, gx = 0.f, gy = 0.f;
+  int step = A.step[e], episode = A.episode[e];
+  if (A.reset_mask && A.reset_mask[e]) {
+    reset_env<float, G>(C, env_id, (uint32_t)episode, i, N, lane, x, y, th, gx, gy);
+    step = 0;
+    if (i == 0) A.reset_mask[e] = 0;
+  } else if (on) {
+    x = A.x[r]; y = A.y[r]; th = A.th[r]; gx = A.gx[r]; gy = A.gy[r];
+  }
+  int nsteps = A.steps;
+  if (A.steps_per_env) nsteps = min(nsteps, A.steps_per_env[e]);
+  const int64_t tb = A.t_start ? A.t_start[e] : (int64_t)A.t0;
+  float s, c;
+  sincosf(th, &s, &c);
+  float rsum = 0.f;
+  for (int k = 0; k < nsteps; ++k) {
+    const int action = drawn_action(C.key0, C.key1, env_id, (uint32_t)(tb + k), i);
+    const StepOut<float> so = env_step_group<float, G>(C, sh, lane, i, N, on, env_id, action, x, y,
+                                                       th, c, s, gx, gy, step, episode, false);
+    rsum += so.reward;
+    if (i == 0) {
+      if (A.reward_out) A.reward_out[(size_t)k * A.E + e] = so.reward;
+      if (A.done_out) A.done_out[(size_t)k * A.E + e] = so.done ? 1 : 0;
+    }
+  }
+  if (on) { A.x[r] = x; A.y[r] = y; A.th[r] = th; A.gx[r] = gx; A.gy[r] = gy; }
+  if (A.obs_final)
+    write_obs<float, G>(A.obs_final + A.obs_off[e] + (size_t)(on ? i : 0) * (2 * N + 4), lane, i,
+                        N, on, x, y, c, s, gx, gy);
+  if (i == 0) {
+    A.step[e] = step;
+    A.episode[e] = episode;
+    if (A.reward_sum) A.reward_sum[e] += rsum;
+    if (A.t_after) A.t_after[e] = tb + nsteps;
+    if (A.steps_left_after && A.steps_per_env) A.steps_left_after[e] = A.steps_per_env[e] - nsteps;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_env_run(RunArgs A) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int tile = blockIdx.x * (blockDim.x >> 6) + wave;
+  if (tile >= A.num_tiles) return;
+  const int4 td = A.tiles[tile];
+  char *mine = lds + (size_t)wave * kMaxWaveLds;
+  switch (td.x) {
+    case 2: run_tile<2>(A, mine, lane, td.y, td.z); break;
+    case 4: run_tile<4>(A, mine, lane, td.y, td.z); break;
+    case 8: run_tile<8>(A, mine, lane, td.y, td.z); break;
+    default: run_tile<16>(A, mine, lane, td.y, td.z); break;
+  }
+}
+
+hipError_t launch_run(const RunArgs &A, int block_threads, hipStream_t st) {
+  const int waves = block_threads / 64;
+  const int blocks = (A.num_tiles + waves - 1) / waves;
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_env_run, dim3(blocks), dim3(block_threads), waves * kMaxWaveLds, st, A);
+  return hipGetLastError();
+}
+
+int lanes_for(const rs_schedule &sched, int n) {
+  const int g = sched.lanes_per_env[n];
+  if (g >= n && g <= 16 && (g & (g - 1)) == 0 && g >= 2) return g;
+  return pow2_group(n);
+}
+
+void build_tiles(const std::vector<int32_t> &envs, const std::vector<int32_t> &nrob_of,
+                 const rs_schedule &sched, std::vector<int32_t> &tiles,
+                 std::vector<int32_t> &items) {
+  std::vector<int32_t> order(envs);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    const int ga = lanes_for(sched, nrob_of[a]), gb = lanes_for(sched, nrob_of[b]);
+    if (ga != gb) return ga < gb;
+    return nrob_of[a] < nrob_of[b];
+  });
+  tiles.clear();
+  items.clear();
+  size_t k = 0;
+  while (k < order.size()) {
+    const int g = lanes_for(sched, nrob_of[order[k]]);
+    const int cap = 64 / g;
+    const int first = (int)items.size();
+    int count = 0;
+    while (k < order.size() && count < cap && lanes_for(sched, nrob_of[order[k]]) == g) {
+      items.push_back(order[k]);
+      ++k;
+      ++count;
+    }
+    tiles.push_back(g);
+    tiles.push_back(first);
+    tiles.push_back(count);
+    tiles.push_back(0);
+  }
+}
+
+static void default_schedule(rs_schedule &s) {
+  std::memset(&s, 0, sizeof(s));
+  s.block_threads = 256;
+}
+
+static rs_status plan_upload(rs_plan *pl) {
+  std::vector<int32_t> envs(pl->num_envs);
+  std::iota(envs.begin(), envs.end(), 0);
+  std::vector<int32_t> tiles, items;
+  build_tiles(envs, pl->robots_host, pl->sched, tiles, items);
+  pl->num_tiles = (int32_t)(tiles.size() / 4);
+  if (pl->tiles_dev) (void)hipFree(pl->tiles_dev);
+  if (pl->items_dev) (void)hipFree(pl->items_dev);
+  pl->tiles_dev = nullptr;
+  pl->items_dev = nullptr;
+  RS_CHECK_HIP(hipMalloc(&pl->tiles_dev, tiles.size() * sizeof(int32_t)));
+  RS_CHECK_HIP(hipMalloc(&pl->items_dev, items.size() * sizeof(int32_t)));
+  RS_CHECK_HIP(hipMemcpy(pl->tiles_dev, tiles.data(), tiles.size() * 4, hipMemcpyHostToDevice));
+  RS_CHECK_HIP(hipMemcpy(pl->items_dev, items.data(), items.size() * 4, hipMemcpyHostToDevice));
+  return RS_OK;
+}
+
+static RunArgs plan_args(const rs_plan *pl, const rs_params *p, const rs_batch *b) {
+  RunArgs A;
+  std::memset(&A, 0, sizeof(A));
+  A.C = make_const<float>(*p);
+  A.E = pl->num_envs;
+  A.num_tiles = pl->num_tiles;
+  A.env_base = (uint32_t)b->env_id_base;
+  A.tiles = reinterpret_cast<const int4 *>(pl->tiles_dev);
+  A.items = pl->items_dev;
+  A.offset = pl->offset_dev;
+  A.nrob = pl->nrob_dev;
+  A.x = (float *)b->x; A.y = (float *)b->y; A.th = (float *)b->theta;
+  A.gx = (float *)b->goal_x; A.gy = (float *)b->goal_y;
+  A.step = b->step; A.episode = b->episode;
+  for (int n = 0; n <= RS_MAX_ROBOTS; ++n)
+    A.qp_iters[n] = pl->sched.qp_iters[n] > 0 ? pl->sched.qp_iters[n] : p->qp_max_iters;
+  return A;
+}
+
+static rs_status check_mixed(const rs_ctx *ctx, const rs_params *p, const rs_plan *plan,
+                             const rs_batch *b) {
+  RS_CHECK_ARG(ctx != nullptr && plan != nullptr && b != nullptr, "ctx/plan/batch is NULL");
+  rs_status s = check_params(p);
+  if (s != RS_OK) return s;
+  RS_CHECK_ARG(p->dtype == RS_F32, "mixed batches run in FP32");
+  RS_CHECK_ARG(p->controller == RS_CTRL_DISCRETE, "env_run drives the discrete controller");
+  RS_CHECK_ARG(b->num_envs == plan->num_envs, "batch has %d envs, plan %d", b->num_envs,
+               plan->num_envs);
+  RS_CHECK_ARG(b->x && b->y && b->theta && b->goal_x && b->goal_y && b->step && b->episode,
+               "state pointer is NULL");
+  return RS_OK;
+}
+
+}  // namespace rs
+
+using namespace rs;
+
+extern "C" {
+
+rs_status rs_plan_create(rs_ctx *ctx, int32_t num_envs, const int32_t *robots_per_env,
+                         const rs_schedule *schedule, rs_plan **out) {
+  RS_CHECK_ARG(ctx != nullptr && out != nullptr, "ctx/out is NULL");
+  RS_CHECK_ARG(num_envs >= 1 && robots_per_env != nullptr, "need num_envs >= 1 and counts");
+  *out = nullptr;
+  rs_plan *pl = new rs_plan();
+  pl->ctx = ctx;
+  pl->num_envs = num_envs;
+  pl->robots_host.assign(robots_per_env, robots_per_env + num_envs);
+  pl->offset_host.resize(num_envs + 1);
+  pl->obs_offset_host.resize(num_envs + 1);
+  int64_t acc = 0, oacc = 0;
+  for (int32_t e = 0; e < num_envs; ++e) {
+    const int n = robots_per_env[e];
+    if (n < 2 || n > RS_MAX_ROBOTS) {
+      delete pl;
+      set_error("robots_per_env[%d] = %d outside 2..16", e, n);
+      return RS_ERR_INVALID_ARG;
+    }
+    pl->offset_host[e] = (int32_t)acc;
+    pl->obs_offset_host[e] = oacc;
+    acc += n;
+    oacc += (int64_t)n * (2 * n + 4);
+  }
+  if (acc > INT32_MAX) {
+    delete pl;
+    set_error("too many robots in one plan");
+    return RS_ERR_INVALID_ARG;
+  }
+  pl->offset_host[num_envs] = (int32_t)acc;
+  pl->obs_offset_host[num_envs] = oacc;
+  pl->total_robots = acc;
+  pl->sched = schedule ? *schedule : ctx->sched;
+  if (pl->sched.block_threads <= 0) pl->sched.block_threads = 256;
+  if (pl->sched.block_threads % 64 != 0 || pl->sched.block_threads > 256) {
+    delete pl;
+    set_error("block_threads must be a multiple of 64 in 64..256");
+    return RS_ERR_INVALID_ARG;
+  }
+  pl->block_threads = pl->sched.block_threads;
+  auto fail = [&](hipError_t e) {
+    set_error("plan allocation failed: %s", hipGetErrorString(e));
+    rs_plan_destroy(pl);
+    return RS_ERR_DEVICE;
+  };
+  hipError_t he;
+  if ((he = hipMalloc(&pl->offset_dev, (num_envs + 1) * sizeof(int32_t))) != hipSuccess) return fail(he);
+  if ((he = hipMalloc(&pl->nrob_dev, num_envs * sizeof(int32_t))) != hipSuccess) return fail(he);
+  if ((he = hipMalloc(&pl->obs_off_dev, (num_envs + 1) * sizeof(int64_t))) != hipSuccess) return fail(he);
+  if ((he = hipMemcpy(pl->offset_dev, pl->offset_host.data(), (num_envs + 1) * 4,
+                      hipMemcpyHostToDevice)) != hipSuccess ||
+      (he = hipMemcpy(pl->nrob_dev, pl->robots_host.data(), num_envs * 4,
+                      hipMemcpyHostToDevice)) != hipSuccess ||
+      (he = hipMemcpy(pl->obs_off_dev, pl->obs_offset_host.data(), (num_envs + 1) * 8,
+                      hipMemcpyHostToDevice)) != hipSuccess)
+    return fail(he);
+  rs_status s = plan_upload(pl);
+  if (s != RS_OK) {
+    rs_plan_destroy(pl);
+    return s;
+  }
+  *out = pl;
+  return RS_OK;
+}
+
+rs_status rs_plan_destroy(rs_plan *pl) {
+  if (!pl) return RS_OK;
+  if (pl->offset_dev) (void)hipFree(pl->offset_dev);
+  if (pl->nrob_dev) (void)hipFree(pl->nrob_dev);
+  if (pl->obs_off_dev) (void)hipFree(pl->obs_off_dev);
+  if (pl->tiles_dev) (void)hipFree(pl->tiles_dev);
+  if (pl->items_dev) (void)hipFree(pl->items_dev);
+  delete pl;
+  return RS_OK;
+}
+
+int64_t rs_plan_total_robots(const rs_plan *plan) { return plan ? plan->total_robots : -1; }
+const int32_t *rs_plan_robot_offset(const rs_plan *plan) { return plan ? plan->offset_dev : nullptr; }
+int64_t rs_plan_obs_offset(const rs_plan *plan, int32_t env) {
+  if (!plan || env < 0 || env > plan->num_envs) return -1;
+  return plan->obs_offset_host[env];
+}
+
+rs_status env_reset_mixed(rs_ctx *ctx, const rs_params *p, const rs_plan *plan, const rs_batch *b,
+                          const uint8_t *mask, void *stream) {
+  rs_status s = check_mixed(ctx, p, plan, b);
+  if (s != RS_OK) return s;
+  RunArgs A = plan_args(plan, p, b);
+  A.steps = 0;
+  // the kernel clears the flags it consumes: work on a scratch copy
+  uint8_t *flags = nullptr;
+  hipStream_t st = (hipStream_t)stream;
+  RS_CHECK_HIP(hipMallocAsync((void **)&flags, plan->num_envs, st));
+  if (mask) {
+    RS_CHECK_HIP(hipMemcpyAsync(flags, mask, plan->num_envs, hipMemcpyDeviceToDevice, st));
+  } else {
+    RS_CHECK_HIP(hipMemsetAsync(flags, 1, plan->num_envs, st));
+  }
+  A.reset_mask = flags;
+  hipError_t he = launch_run(A, plan->block_threads, st);
+  (void)hipFreeAsync(flags, st);
+  if (he != hipSuccess) {
+    set_error("env_reset_mixed launch failed: %s", hipGetErrorString(he));
+    return RS_ERR_DEVICE;
+  }
+  return RS_OK;
+}
+
+rs_status env_run(rs_ctx *ctx, const rs_params *p, const rs_plan *plan, const rs_batch *b,
+                  int32_t steps, const int64_t *t_start, int64_t t_global0,
+                  const int32_t *steps_per_env, float *reward_out, uint8_t *done_out,
+                  float *reward_sum, float *obs_final, void *stream) {
+  rs_status s = check_mixed(ctx, p, plan, b);
+  if (s != RS_OK) return s;
+  RS_CHECK_ARG(steps >= 0, "steps must be >= 0");
+  RunArgs A = plan_args(plan, p, b);
+  A.steps = steps;
+  A.t0 = (uint32_t)t_global0;
+  A.t_start = t_start;
+  A.steps_per_env = steps_per_env;
+  A.reward_out = reward_out;
+  A.done_out = done_out;
+  A.reward_sum = reward_sum;
+  A.obs_final = obs_final;
+  A.obs_off = plan->obs_off_dev;
+  hipError_t he = launch_run(A, plan->block_threads, (hipStream_t)stream);
+  if (he != hipSuccess) {
+    set_error("env_run launch failed: %s", hipGetErrorString(he));
+    return RS_ERR_DEVICE;
+  }
+  return RS_OK;
+}
+
+rs_status rs_get_schedule(rs_ctx *ctx, rs_schedule *out) {
+  RS_CHECK_ARG(ctx != nullptr && out != nullptr, "ctx/out is NULL");
+  *out = ctx->sched;
+  return RS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner
+// ---------------------------------------------------------------------------
+rs_status rs_autotune(rs_ctx *ctx, const rs_params *p, const int32_t *robots, int32_t count,
+                      int32_t envs, int32_t steps, double tol, rs_schedule *out) {
+  RS_CHECK_ARG(ctx != nullptr && robots != nullptr && count >= 1, "ctx/robots invalid");
+  RS_CHECK_ARG(envs >= 1 && steps >= 1 && tol > 0, "envs, steps, tol must be > 0");
+  rs_status s = check_params(p);
+  if (s != RS_OK) return s;
+  RS_CHECK_ARG(p->dtype == RS_F32 && p->controller == RS_CTRL_DISCRETE,
+               "autotune runs the FP32 discrete-controller path");
+  hipStream_t st;
+  RS_CHECK_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  hipEvent_t ev0, ev1;
+  RS_CHECK_HIP(hipEventCreate(&ev0));
+  RS_CHECK_HIP(hipEventCreate(&ev1));
+  rs_status result = RS_OK;
+  for (int32_t k = 0; k < count && result == RS_OK; ++k) {
+    const int n = robots[k];
+    if (n < 2 || n > RS_MAX_ROBOTS) {
+      set_error("robots[%d] = %d outside 2..16", k, n);
+      result = RS_ERR_INVALID_ARG;
+      break;
+    }
+    const size_t R = (size_t)envs * n;
+    // synthetic workload: reset-sampled envs, and every other env packed in a
+    // cluster of pitch 0.2 m around the arena centre so the certificate binds
+    std::vector<float> hx(R), hy(R), hth(R), hgx(R), hgy(R);
+    float *dbuf = nullptr;
+    int32_t *ibuf = nullptr;
+    if (hipMalloc(&dbuf, 10 * R * sizeof(float)) != hipSuccess ||
+        hipMalloc(&ibuf, 2 * (size_t)envs * sizeof(int32_t)) != hipSuccess) {
+      set_error("autotune allocation failed");
+      result = RS_ERR_OUT_OF_MEMORY;
+      break;
+    }
+    rs_batch b;
+    std::memset(&b, 0, sizeof(b));
+    b.num_envs = envs;
+    b.robots = n;
+    float *f = dbuf;
+    b.x = f; b.y = f + R; b.theta = f + 2 * R; b.goal_x = f + 3 * R; b.goal_y = f + 4 * R;
+    float *init = f + 5 * R;  // pristine copy of the 5 fields
+    b.step = ibuf;
+    b.episode = ibuf + envs;
+    std::vector<int32_t> counts(envs, n);
+    rs_schedule ref_s;
+    default_schedule(ref_s);
+    rs_plan *ref_plan = nullptr;
+    s = rs_plan_create(ctx, envs, counts.data(), &ref_s, &ref_plan);
+    if (s != RS_OK) { result = s; (void)hipFree(dbuf); (void)hipFree(ibuf); break; }
+    (void)hipMemsetAsync(ibuf, 0, 2 * (size_t)envs * sizeof(int32_t), st);
+    s = env_reset_mixed(ctx, p, ref_plan, &b, nullptr, st);
+    (void)hipStreamSynchronize(st);
+    (void)hipMemcpy(hx.data(), b.x, R * 4, hipMemcpyDeviceToHost);
+    (void)hipMemcpy(hy.data(), b.y, R * 4, hipMemcpyDeviceToHost);
+    const int side = (int)std::ceil(std::sqrt((double)n));
+    for (int32_t e = 1; e < envs; e += 2) {
+      for (int i = 0; i < n; ++i) {
+        hx[(size_t)e * n + i] = -0.3f + 0.2f * (float)(i % side);
+        hy[(size_t)e * n + i] = -0.3f + 0.2f * (float)(i / side);
+      }
+    }
+    (void)hipMemcpy(b.x, hx.data(), R * 4, hipMemcpyHostToDevice);
+    (void)hipMemcpy(b.y, hy.data(), R * 4, hipMemcpyHostToDevice);
+    (void)hipMemcpy(init, dbuf, 5 * R * 4, hipMemcpyDeviceToDevice);
+    auto restore = [&]() {
+      (void)hipMemcpyAsync(dbuf, init, 5 * R * 4, hipMemcpyDeviceToDevice, st);
+      (void)hipMemsetAsync(ibuf, 0, 2 * (size_t)envs * sizeof(int32_t), st);
+    };
+    // reference: smallest lanes, widest cap
+    ref_s.qp_iters[n] = 8 * n + 32;
+    rs_plan_destroy(ref_plan);
+    ref_plan = nullptr;
+    rs_plan_create(ctx, envs, counts.data(), &ref_s, &ref_plan);
+    restore();
+    env_run(ctx, p, ref_plan, &b, steps, nullptr, 0, nullptr, nullptr, nullptr, nullptr, nullptr, st);
+    (void)hipStreamSynchronize(st);
+    std::vector<float> rx(R), ry(R), cx(R), cy(R);
+    (void)hipMemcpy(rx.data(), b.x, R * 4, hipMemcpyDeviceToHost);
+    (void)hipMemcpy(ry.data(), b.y, R * 4, hipMemcpyDeviceToHost);
+    rs_plan_destroy(ref_plan);
+    const double bound = steps * p->dt * tol;
+    const int g0 = pow2_group(n);
+    float best_ms = 1e30f;
+    int best_g = g0, best_block = 256, best_cap = 8 * n + 32;
+    const int caps[3] = {2 * n + 4, 4 * n + 8, 8 * n + 32};
+    for (int g = g0; g <= 16; g *= 2) {
+      if (g > g0 * 2) break;
+      for (int blk = 64; blk <= 256; blk *= 2) {
+        for (int ci = 0; ci < 3; ++ci) {
+          rs_schedule cs;
+          default_schedule(cs);
+          cs.block_threads = blk;
+          cs.lanes_per_env[n] = g;
+          cs.qp_iters[n] = caps[ci];
+          rs_plan *pl = nullptr;
+          if (rs_plan_create(ctx, envs, counts.data(), &cs, &pl) != RS_OK) continue;
+          float ms = 1e30f;
+          bool ok = true;
+          for (int rep = 0; rep < 3 && ok; ++rep) {
+            restore();
+            (void)hipEventRecord(ev0, st);
+            env_run(ctx, p, pl, &b, steps, nullptr, 0, nullptr, nullptr, nullptr, nullptr, nullptr, st);
+            (void)hipEventRecord(ev1, st);
+            (void)hipEventSynchronize(ev1);
+            float t = 0.f;
+            (void)hipEventElapsedTime(&t, ev0, ev1);
+            ms = std::min(ms, t);
+            if (rep == 0) {
+              (void)hipMemcpy(cx.data(), b.x, R * 4, hipMemcpyDeviceToHost);
+              (void)hipMemcpy(cy.data(), b.y, R * 4, hipMemcpyDeviceToHost);
+              double worst = 0.0;
+              for (size_t q = 0; q < R; ++q)
+                worst = std::max(worst, (double)std::max(std::fabs(cx[q] - rx[q]),
+                                                         std::fabs(cy[q] - ry[q])));
+              ok = worst <= bound;
+            }
+          }
+          rs_plan_destroy(pl);
+          if (ok && ms < best_ms * 0.98f) {
+            best_ms = ms;
+            best_g = g;
+            best_block = blk;
+            best_cap = caps[ci];
+          }
+        }
+      }
+    }
+    ctx->sched.lanes_per_env[n] = best_g;
+    ctx->sched.qp_iters[n] = best_cap;
+    ctx->sched.block_threads = best_block;
+    (void)hipFree(dbuf);
+    (void)hipFree(ibuf);
+  }
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
+  (void)hipStreamDestroy(st);
+  if (out) *out = ctx->sched;
+  return result;
+}
+
+}  // extern "C"

@@ -1,0 +1,384 @@
+// rs_qp.hpp -- barrier-certificate QP of one environment, solved exactly by
+// the lane group that owns it.
+//
+// Problem (control barrier certificate of JaxRobotarium Sec. 4.1, with the
+// cubic class-K pairwise rows and wall rows defined in robostep.h):
+//     min |u - u_nom|^2   s.t.  -2 D_ij.u_i + 2 D_ij.u_j <= gamma h_ij^3  (i<j)
+//                               lo_i <= u_i <= hi_i                     (per coordinate)
+// The minimiser is the Euclidean projection of u_nom onto a polytope, hence
+// unique. It is found with a dual active-set method in the style of Goldfarb
+// and Idnani (1983) specialised to the identity Hessian:
+//   * bound rows are unit rows, so an active bound simply fixes its coordinate;
+//     the active pairwise rows S enter a Gram system restricted to the free
+//     coordinates, G_S = C_S^free C_S^free^T (q x q, q small), factored by
+//     Cholesky in LDS;
+//   * the start point clips u_nom to the box, which is exactly the state after
+//     adding every violated bound (they are mutually orthogonal);
+//   * each iteration adds the most violated row (normalised violation),
+//     stepping along its component z orthogonal to the active set and
+//     dropping an active row whose multiplier would turn negative.
+// Rows that no point of the speed box can violate (4 v_max (|Dx|+|Dy|) <= b)
+// are never examined: they are implied by the box, so the solution is
+// unchanged.
+//
+// Work split inside the group: lane i owns robot i (its u, bounds, fixed
+// flags and bound multipliers) and the pairs (i, i+k mod N), k = 1..N/2
+// (k = N/2 only for i < N/2), so every pair has exactly one owner and the
+// violation scan costs ceil((N-1)/2) rounds. The q x q algebra is done
+// identically by every lane of the group from group-uniform data.
+#pragma once
+
+#include "rs_device.hpp"
+
+namespace rs {
+
+template <typename T, int G> struct QPScratch {
+  int act[2 * G];           // active pair rows: a | b << 8, a < b
+  T dx[2 * G], dy[2 * G];   // D = p_a - p_b of each active row
+  T lam[2 * G];             // multipliers (objective 1/2 |u - u_nom|^2)
+  T rv[2 * G];              // r = G_S^-1 g
+  T L[(2 * G) * (2 * G + 1) / 2];  // packed lower Cholesky factor of G_S
+};
+
+__device__ __forceinline__ int tri(int a, int b) { return (a * (a + 1)) / 2 + b; }
+
+// Owner lane and rotation distance of pair (a, b), a < b, among N robots.
+__device__ __forceinline__ void pair_owner(int a, int b, int N, int &owner, int &k) {
+  const int d = b - a;
+  if (2 * d <= N) {
+    owner = a;
+    k = d;
+  } else {
+    owner = b;
+    k = N - d;
+  }
+}
+
+// Index of pair (a, b), a < b, in lexicographic order.
+__device__ __forceinline__ int pair_index(int a, int b, int N) {
+  return a * (2 * N - a - 1) / 2 + (b - a - 1);
+}
+
+template <typename T> __device__ __forceinline__ T tmax(T a, T b) { return a > b ? a : b; }
+template <typename T> __device__ __forceinline__ T tmin(T a, T b) { return a < b ? a : b; }
+template <typename T> __device__ __forceinline__ T tabs(T a) { return a < T(0) ? -a : a; }
+template <typename T> __device__ __forceinline__ T big_v();
+template <> __device__ __forceinline__ float big_v<float>() { return 3.0e38f; }
+template <> __device__ __forceinline__ double big_v<double>() { return 1.0e300; }
+
+// Per-coordinate bounds: speed box intersected with the wall certificates of
+// the projection point (walls pulled in by r_s / 2, gain c_b gamma, cubic).
+template <typename T>
+__device__ __forceinline__ void wall_bounds(const SimConst<T> &C, T px, T py, T &lox, T &hix,
+                                            T &loy, T &hiy) {
+  const T mxh = C.x_max - C.half - px, mxl = px - C.x_min - C.half;
+  const T myh = C.y_max - C.half - py, myl = py - C.y_min - C.half;
+  hix = tmin(C.vmax, C.kb * (mxh * mxh * mxh));
+  lox = tmax(-C.vmax, -(C.kb * (mxl * mxl * mxl)));
+  hiy = tmin(C.vmax, C.kb * (myh * myh * myh));
+  loy = tmax(-C.vmax, -(C.kb * (myl * myl * myl)));
+}
+
+// Gram entry of active rows s, t over the free coordinates.
+template <typename T>
+__device__ __forceinline__ T gram_entry(int as, int bs, T dxs, T dys, int at, int bt, T dxt,
+                                        T dyt, uint32_t freex, uint32_t freey) {
+  T acc = T(0);
+  // robot shared as the "a" (sign -) or "b" (sign +) end of each row
+  const int ends_s[2] = {as, bs};
+  const int ends_t[2] = {at, bt};
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      const int r = ends_s[u];
+      if (r == ends_t[v]) {
+        const T sg = (u == v) ? T(4) : T(-4);
+        T dd = T(0);
+        if ((freex >> r) & 1u) dd += dxs * dxt;
+        if ((freey >> r) & 1u) dd += dys * dyt;
+        acc += sg * dd;
+      }
+    }
+  }
+  return acc;
+}
+
+struct QPInfo {
+  int status;  // 0 solved, 1 infeasible, 2 iteration cap / numerical failure
+  int iters;   // active-set iterations
+  int q;       // active pairwise rows at exit (in sh->act / sh->lam)
+};
+
+// Solve the certificate for the group's environment. Every lane of the group
+// must call this together (uniform control flow within the group). `i` is the
+// robot index (lane in group), `on` = i < N. On return (ux, uy) is the
+// command; for status 1 it is the per-coordinate fallback.
+template <typename T, int G>
+__device__ QPInfo qp_solve(QPScratch<T, G> *sh, const SimConst<T> &C, int lane, int i, int N,
+                           bool on, T px, T py, T uhx, T uhy, T lox, T hix, T loy, T hiy, T &ux,
+                           T &uy) {
+  const int base = lane & ~(G - 1);
+  const T BIG = big_v<T>();
+  QPInfo info{0, 0, 0};
+
+  // --- empty box: infeasible, closed-form fallback -------------------------
+  const bool crossed = on && (lox > hix || loy > hiy);
+  bool dead = group_any<G>(crossed, lane);
+
+  // --- start: clip to the box; active bounds fix their coordinate ----------
+  int fx = 0, fy = 0;  // +1 fixed at upper, -1 fixed at lower
+  T mux = T(0), muy = T(0);
+  ux = uhx;
+  uy = uhy;
+  if (on) {
+    if (uhx > hix) { ux = hix; fx = 1; mux = uhx - hix; }
+    else if (uhx < lox) { ux = lox; fx = -1; mux = lox - uhx; }
+    if (uhy > hiy) { uy = hiy; fy = 1; muy = uhy - hiy; }
+    else if (uhy < loy) { uy = loy; fy = -1; muy = loy - uhy; }
+  }
+
+  int q = 0;
+  uint32_t own_act = 0;  // bit k: my rotation-k pair is active
+  const int cap = C.qp_cap > 0 ? C.qp_cap : 8 * N + 32;
+  const int K = N >> 1;
+
+  while (!dead) {
+    // --- most violated constraint ------------------------------------------
+    T best = C.tol_add;
+    int bid = -1;  // pair: a << 4 | b ; bound: 256 + 4 i + 2 coord + (lower)
+    bool coincide = false;
+    if (on) {
+      if (fx == 0) {
+        const T su = ux - hix, sl = lox - ux;
+        if (su > best) { best = su; bid = 256 + 4 * i; }
+        else if (sl > best) { best = sl; bid = 256 + 4 * i + 1; }
+      }
+      if (fy == 0) {
+        const T su = uy - hiy, sl = loy - uy;
+        if (su > best) { best = su; bid = 256 + 4 * i + 2; }
+        else if (sl > best) { best = sl; bid = 256 + 4 * i + 3; }
+      }
+    }
+    for (int k = 1; k <= K; ++k) {
+      const int j = on ? (i + k >= N ? i + k - N : i + k) : 0;
+      const T pxj = __shfl(px, base + j, 64), pyj = __shfl(py, base + j, 64);
+      const T uxj = __shfl(ux, base + j, 64), uyj = __shfl(uy, base + j, 64);
+      const bool mine = on && !(2 * k == N && i >= k) && !((own_act >> k) & 1u);
+      if (mine) {
+        const bool ia = i < j;
+        const T dx = ia ? px - pxj : pxj - px;
+        const T dy = ia ? py - pyj : pyj - py;
+        const T d2 = dx * dx + dy * dy;
+        const T h = d2 - C.rs2;
+        const T bb = C.gamma * (h * h * h);
+        if (T(4) * C.vmax * (tabs(dx) + tabs(dy)) > bb) {
+          const T dux = ia ? uxj - ux : ux - uxj;  // u_b - u_a
+          const T duy = ia ? uyj - uy : uy - uyj;
+          const T s = T(2) * (dx * dux + dy * duy) - bb;
+          if (d2 > T(0)) {
+            const T sn = s / (T(2.8284271247461903) * sqrt_t(d2));
+            if (sn > best) {
+              best = sn;
+              bid = (ia ? i : j) << 4 | (ia ? j : i);
+            }
+          } else if (bb < T(0)) {
+            coincide = true;
+          }
+        }
+      }
+    }
+    if (group_any<G>(coincide, lane)) { dead = true; break; }
+    group_argmax<G>(best, bid);
+    if (bid < 0) break;  // optimal
+    if (++info.iters > cap) { info.status = 2; break; }
+
+    // --- constraint p -------------------------------------------------------
+    const bool p_pair = bid < 256;
+    const int pa = p_pair ? (bid >> 4) : ((bid - 256) >> 2);
+    const int pb = p_pair ? (bid & 15) : 0;
+    const int pk = p_pair ? 0 : (((bid - 256) >> 1) & 1);     // bound coordinate
+    const int psig = p_pair ? 0 : (((bid - 256) & 1) ? -1 : 1);  // +1 upper
+    T dpx = T(0), dpy = T(0), bp = T(0);
+    {
+      const T xa = __shfl(px, base + pa, 64), ya = __shfl(py, base + pa, 64);
+      const T xb = __shfl(px, base + pb, 64), yb = __shfl(py, base + pb, 64);
+      if (p_pair) {
+        dpx = xa - xb;
+        dpy = ya - yb;
+        const T h = dpx * dpx + dpy * dpy - C.rs2;
+        bp = C.gamma * (h * h * h);
+      }
+    }
+    T lam_p = T(0);
+    bool added = false;
+    for (int inner = 0; inner < cap && !added; ++inner) {
+      const uint32_t freex = ~group_bits<G>(__ballot(fx != 0), lane);
+      const uint32_t freey = ~group_bits<G>(__ballot(fy != 0), lane);
+      // Gram system of the active rows over the free coordinates
+      bool chol_ok = true;
+      for (int a = 0; a < q && chol_ok; ++a) {
+        const int acta = sh->act[a];
+        const int aa = acta & 255, ab = acta >> 8;
+        const T adx = sh->dx[a], ady = sh->dy[a];
+        for (int b = 0; b <= a; ++b) {
+          const int actb = sh->act[b];
+          T s = gram_entry<T>(aa, ab, adx, ady, actb & 255, actb >> 8, sh->dx[b], sh->dy[b], freex,
+                              freey);
+          for (int k2 = 0; k2 < b; ++k2) s -= sh->L[tri(a, k2)] * sh->L[tri(b, k2)];
+          if (a == b) {
+            if (!(s > T(0))) { chol_ok = false; break; }
+            sh->L[tri(a, a)] = sqrt_t(s);
+          } else {
+            sh->L[tri(a, b)] = s / sh->L[tri(b, b)];
+          }
+        }
+      }
+      if (!chol_ok) { info.status = 2; break; }
+      // g = C_S^free c_p, then r = G_S^-1 g (forward, backward substitution)
+      for (int a = 0; a < q; ++a) {
+        const int acta = sh->act[a];
+        const int aa = acta & 255, ab = acta >> 8;
+        T g;
+        if (p_pair) {
+          g = gram_entry<T>(aa, ab, sh->dx[a], sh->dy[a], pa, pb, dpx, dpy, freex, freey);
+        } else {
+          const T comp = pk ? sh->dy[a] : sh->dx[a];
+          g = (pa == aa) ? T(-2) * comp : ((pa == ab) ? T(2) * comp : T(0));
+          g *= T(psig);
+        }
+        for (int k2 = 0; k2 < a; ++k2) g -= sh->L[tri(a, k2)] * sh->rv[k2];
+        sh->rv[a] = g / sh->L[tri(a, a)];
+      }
+      for (int a = q - 1; a >= 0; --a) {
+        T s = sh->rv[a];
+        for (int k2 = a + 1; k2 < q; ++k2) s -= sh->L[tri(k2, a)] * sh->rv[k2];
+        sh->rv[a] = s / sh->L[tri(a, a)];
+      }
+      // (C_S^T r) and c_p at my robot
+      T crx = T(0), cry = T(0);
+      for (int a = 0; a < q; ++a) {
+        const int acta = sh->act[a];
+        const T ra = sh->rv[a];
+        if (i == (acta & 255)) { crx -= T(2) * sh->dx[a] * ra; cry -= T(2) * sh->dy[a] * ra; }
+        else if (i == (acta >> 8)) { crx += T(2) * sh->dx[a] * ra; cry += T(2) * sh->dy[a] * ra; }
+      }
+      T cpx = T(0), cpy = T(0);
+      if (p_pair) {
+        if (i == pa) { cpx = T(-2) * dpx; cpy = T(-2) * dpy; }
+        else if (i == pb) { cpx = T(2) * dpx; cpy = T(2) * dpy; }
+      } else if (i == pa) {
+        if (pk) cpy = T(psig); else cpx = T(psig);
+      }
+      if (!on) { crx = cry = cpx = cpy = T(0); }
+      const T zx = fx == 0 ? cpx - crx : T(0);
+      const T zy = fy == 0 ? cpy - cry : T(0);
+      const T rfx = fx != 0 ? T(fx) * (cpx - crx) : T(0);
+      const T rfy = fy != 0 ? T(fy) * (cpy - cry) : T(0);
+      const T zz = group_sum<G>(zx * zx + zy * zy);
+      T cpn2;
+      if (p_pair) {
+        T sa = T(0), sb = T(0);
+        if ((freex >> pa) & 1u) sa += dpx * dpx;
+        if ((freey >> pa) & 1u) sa += dpy * dpy;
+        if ((freex >> pb) & 1u) sb += dpx * dpx;
+        if ((freey >> pb) & 1u) sb += dpy * dpy;
+        cpn2 = T(4) * (sa + sb);
+      } else {
+        cpn2 = T(1);
+      }
+      // blocking step t1: active rows first (uniform), then my fixed bounds
+      T t1 = BIG;
+      int drop = -1;  // pair slot, or 1024 + 2 robot + coord for a bound
+      for (int a = 0; a < q; ++a) {
+        const T ra = sh->rv[a];
+        if (ra > C.eps_r) {
+          const T ratio = sh->lam[a] / ra;
+          if (ratio < t1) { t1 = ratio; drop = a; }
+        }
+      }
+      if (on && fx != 0 && rfx > C.eps_r) {
+        const T ratio = mux / rfx;
+        if (ratio < t1 || (ratio == t1 && drop < 0)) { t1 = ratio; drop = 1024 + 2 * i; }
+      }
+      if (on && fy != 0 && rfy > C.eps_r) {
+        const T ratio = muy / rfy;
+        if (ratio < t1 || (ratio == t1 && drop < 0)) { t1 = ratio; drop = 1024 + 2 * i + 1; }
+      }
+      group_argmin<G>(t1, drop);
+      // current violation of p
+      T sp;
+      if (p_pair) {
+        const T uxa = __shfl(ux, base + pa, 64), uya = __shfl(uy, base + pa, 64);
+        const T uxb = __shfl(ux, base + pb, 64), uyb = __shfl(uy, base + pb, 64);
+        sp = T(2) * (dpx * (uxb - uxa) + dpy * (uyb - uya)) - bp;
+      } else {
+        const T mine = pk ? (psig > 0 ? uy - hiy : loy - uy) : (psig > 0 ? ux - hix : lox - ux);
+        sp = __shfl(mine, base + pa, 64);
+      }
+      const bool z_ok = zz > C.eps_z * cpn2;
+      const T t2 = z_ok ? sp / zz : BIG;
+      if (drop < 0 && !z_ok) { dead = true; break; }  // no step can restore p
+      const bool full = z_ok && (drop < 0 || t2 <= t1);
+      const T t = full ? t2 : t1;
+      if (z_ok) {
+        ux -= t * zx;
+        uy -= t * zy;
+      }
+      for (int a = 0; a < q; ++a) sh->lam[a] = sh->lam[a] - t * sh->rv[a];
+      if (on) {
+        mux -= t * rfx;
+        muy -= t * rfy;
+      }
+      lam_p += t;
+      if (full) {
+        if (p_pair) {
+          if (q >= 2 * G) { info.status = 2; break; }
+          sh->act[q] = pa | (pb << 8);
+          sh->dx[q] = dpx;
+          sh->dy[q] = dpy;
+          sh->lam[q] = lam_p;
+          ++q;
+          int owner, kk;
+          pair_owner(pa, pb, N, owner, kk);
+          if (i == owner) own_act |= 1u << kk;
+        } else if (i == pa) {
+          if (pk) { fy = psig; muy = lam_p; uy = psig > 0 ? hiy : loy; }
+          else { fx = psig; mux = lam_p; ux = psig > 0 ? hix : lox; }
+        }
+        added = true;
+      } else if (drop >= 1024) {
+        const int r = (drop - 1024) >> 1, c = (drop - 1024) & 1;
+        if (i == r) {
+          if (c) { fy = 0; muy = T(0); } else { fx = 0; mux = T(0); }
+        }
+      } else {
+        const int act = sh->act[drop];
+        int owner, kk;
+        pair_owner(act & 255, act >> 8, N, owner, kk);
+        if (i == owner) own_act &= ~(1u << kk);
+        for (int a = drop; a + 1 < q; ++a) {
+          sh->act[a] = sh->act[a + 1];
+          sh->dx[a] = sh->dx[a + 1];
+          sh->dy[a] = sh->dy[a + 1];
+          sh->lam[a] = sh->lam[a + 1];
+        }
+        --q;
+      }
+      if (++info.iters > cap) { info.status = 2; break; }
+    }
+    if (info.status == 2 || dead) break;
+  }
+
+  if (dead) {
+    info.status = 1;
+    if (on) {
+      ux = lox <= hix ? tmin(tmax(uhx, lox), hix) : T(0.5) * (lox + hix);
+      uy = loy <= hiy ? tmin(tmax(uhy, loy), hiy) : T(0.5) * (loy + hiy);
+    }
+  }
+  info.q = dead ? 0 : q;
+  return info;
+}
+
+}  // namespace rs

@@ -1,0 +1,346 @@
+// rs_rollout.hip -- fused, persistent policy rollout (FP32 state, bf16 MLP on
+// MFMA) and its C-ABI entry point.
+//
+// One launch runs all H steps: the state of every robot stays in registers,
+// each wavefront owns 64/G environments (lane i of a G-lane group = robot i).
+// Per step and wavefront:
+//   1. observation rows (2N+4 floats) are built in registers and staged in LDS
+//      packed env after env, then copied to HBM with 16-byte vector stores
+//      that cover one contiguous range per wavefront;
+//   2. the policy runs transposed on v_mfma_f32_16x16x32_bf16: for each tile
+//      of 16 robots, H1^T = W1^T X^T (K = 32 features), H2^T = W2^T H1^T,
+//      logits^T = W3^T H2^T (K = 64 in two steps). The K order of layers 2-3
+//      is permuted so that the accumulator registers of one layer are the
+//      B operand of the next, with no LDS round trip; weights are permuted the
+//      same way when they are loaded into registers at kernel start, and the
+//      biases seed the accumulators;
+//   3. logits go through LDS back to the robot's lane, which draws its action
+//      by inverse CDF from its own counter-based uniform;
+//   4. the env step (certificate QP, dynamics, reward, reset) runs as in
+//      env_step.
+#include "rs_internal.hpp"
+#include "rs_step.hpp"
+
+#include <cstring>
+
+namespace rs {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kRollBlock = 256;
+constexpr int kRollWaves = kRollBlock / 64;
+
+struct RolloutArgs {
+  SimConst<float> C;
+  int E, N, D, H;
+  uint32_t env_base, t0;
+  float *x, *y, *th, *gx, *gy;
+  int32_t *step, *episode;
+  const __bf16 *w1, *w2, *w3;
+  const float *b1, *b2, *b3;
+  float *obs;
+  uint8_t *actions;
+  float *reward;
+  uint8_t *done;
+};
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Hidden index held in slot j of lane group g at k-step s of layers 2 and 3:
+// the accumulator of output tile (2s + j/4), register j%4, of lane group g.
+__device__ __forceinline__ int perm_hidden(int s, int g, int j) {
+  return 16 * (2 * s + (j >> 2)) + 4 * g + (j & 3);
+}
+
+template <int G>
+__global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
+  constexpr int EPW = 64 / G;
+  __shared__ QPScratch<float, G> qs[kRollBlock / G];
+  __shared__ __attribute__((aligned(16))) float obs_lds[kRollWaves][64 * 32];
+  __shared__ float4 logit_lds[kRollWaves][64 * 2];
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int i = lane & (G - 1);
+  const int grp = lane / G;
+  const int e0 = (blockIdx.x * kRollWaves + wave) * EPW;
+  if (e0 >= A.E) return;  // the whole wavefront leaves together
+  const int e = e0 + grp;
+  const int N = A.N, D = A.D;
+  const bool env_ok = e < A.E;
+  const bool on = env_ok && i < N;
+  const int nenv = min(EPW, A.E - e0);
+  const size_t r = on ? (size_t)e * N + i : 0;
+
+  float x = 0.f, y = 0.f, th = 0.f, gx = 0.f, gy = 0.f;
+  int step = 0, episode = 0;
+  if (on) { x = A.x[r]; y = A.y[r]; th = A.th[r]; gx = A.gx[r]; gy = A.gy[r]; }
+  if (env_ok) { step = A.step[e]; episode = A.episode[e]; }
+  float s, c;
+  sincosf(th, &s, &c);
+
+  // ---- policy weights into registers (MFMA A-operand fragments) ----------
+  const int g = lane >> 4, c16 = lane & 15;
+  bf16x8 w1f[4], w2f[4][2], w3f[2];
+  floatx4 b1f[4], b2f[4], b3f;
+  const __bf16 zero = (__bf16)0.0f;
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int f = 8 * g + j;
+      w1f[mt][j] = f < D ? A.w1[f * 64 + 16 * mt + c16] : zero;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      b1f[mt][j] = A.b1[16 * mt + 4 * g + j];
+      b2f[mt][j] = A.b2[16 * mt + 4 * g + j];
+    }
+#pragma unroll
+    for (int sk = 0; sk < 2; ++sk)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) w2f[mt][sk][j] = A.w2[perm_hidden(sk, g, j) * 64 + 16 * mt + c16];
+  }
+#pragma unroll
+  for (int sk = 0; sk < 2; ++sk)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) w3f[sk][j] = c16 < 5 ? A.w3[perm_hidden(sk, g, j) * 5 + c16] : zero;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) b3f[j] = (4 * g + j) < 5 ? A.b3[4 * g + j] : 0.0f;
+
+  float *obs_w = obs_lds[wave];
+  float4 *logit_w = logit_lds[wave];
+  QPScratch<float, G> *sh = &qs[threadIdx.x / G];
+  const int base = lane & ~(G - 1);
+  const int nfl = nenv * N * D;             // floats of this wavefront's rows
+  const bool vec4 = ((N * D) & 3) == 0;
+  const int row = grp * N + i;              // packed LDS row of my robot
+
+  for (int t = 0; t < A.H; ++t) {
+    // ---- 1. observation -> LDS (packed) -> HBM --------------------------
+    float *o = obs_w + row * D;
+    if (on) { o[0] = x; o[1] = y; o[2] = c; o[3] = s; }
+    for (int j = 0; j < N; ++j) {
+      const float xj = __shfl(x, base + j, 64), yj = __shfl(y, base + j, 64);
+      if (on && j != i) {
+        const int m = 4 + 2 * (j < i ? j : j - 1);
+        o[m] = xj - x;
+        o[m + 1] = yj - y;
+      }
+    }
+    if (on) { o[D - 2] = gx - x; o[D - 1] = gy - y; }
+    wave_lds_sync();
+    if (A.obs) {
+      float *dst = A.obs + ((size_t)t * A.E + e0) * (size_t)(N * D);
+      if (vec4) {
+        for (int q = lane; q < (nfl >> 2); q += 64)
+          reinterpret_cast<float4 *>(dst)[q] = reinterpret_cast<const float4 *>(obs_w)[q];
+      } else {
+        for (int q = lane; q < (nfl >> 1); q += 64)
+          reinterpret_cast<float2 *>(dst)[q] = reinterpret_cast<const float2 *>(obs_w)[q];
+      }
+    }
+
+    // ---- 2. policy MLP on MFMA, one tile of 16 robots at a time ----------
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const int n = 16 * nt + c16;  // wave lane of the robot in this column
+      const int ng = n / G, ni = n & (G - 1);
+      const bool nvalid = ni < N && ng < nenv;
+      const float *src = obs_w + (ng * N + ni) * D;
+      bf16x8 xb;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int f = 8 * g + j;
+        xb[j] = (nvalid && f < D) ? (__bf16)src[f] : zero;
+      }
+      floatx4 h1[4];
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt)
+        h1[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1f[mt], xb, b1f[mt], 0, 0, 0);
+      bf16x8 hb[2];
+#pragma unroll
+      for (int sk = 0; sk < 2; ++sk)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) hb[sk][j] = (__bf16)fmaxf(h1[2 * sk + (j >> 2)][j & 3], 0.0f);
+      floatx4 h2[4];
+#pragma unroll
+      for (int mo = 0; mo < 4; ++mo) {
+        h2[mo] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2f[mo][0], hb[0], b2f[mo], 0, 0, 0);
+        h2[mo] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2f[mo][1], hb[1], h2[mo], 0, 0, 0);
+      }
+      bf16x8 hc[2];
+#pragma unroll
+      for (int sk = 0; sk < 2; ++sk)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) hc[sk][j] = (__bf16)fmaxf(h2[2 * sk + (j >> 2)][j & 3], 0.0f);
+      floatx4 lg = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3f[0], hc[0], b3f, 0, 0, 0);
+      lg = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3f[1], hc[1], lg, 0, 0, 0);
+      // lane (g, c16) holds logits 4g..4g+3 of robot n
+      if (g < 2) logit_w[n * 2 + g] = make_float4(lg[0], lg[1], lg[2], lg[3]);
+    }
+    wave_lds_sync();
+
+    // ---- 3. categorical draw in the robot's own lane ----------------------
+    const float4 la = logit_w[lane * 2], lb = logit_w[lane * 2 + 1];
+    const float l5[5] = {la.x, la.y, la.z, la.w, lb.x};
+    float mx = l5[0];
+#pragma unroll
+    for (int k = 1; k < 5; ++k) mx = fmaxf(mx, l5[k]);
+    float ex[5], tot = 0.f;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) { ex[k] = expf(l5[k] - mx); tot += ex[k]; }
+    const uint32_t env_id = A.env_base + (uint32_t)e;
+    const uint4 pb = stream_block(A.C.key0, A.C.key1, env_id, A.t0 + (uint32_t)t, kPolicy,
+                                  (uint32_t)(i >> 2), 0u);
+    const float u = unit24(word(pb, i & 3));
+    int action = 4;
+    float cdf = 0.f;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      cdf += ex[k] / tot;
+      if (action == 4 && k < 4 && u < cdf) action = k;
+    }
+    if (on) A.actions[((size_t)t * A.E + e) * N + i] = (uint8_t)action;
+
+    // ---- 4. env step --------------------------------------------------------
+    if (env_ok) {
+      const StepOut<float> so = env_step_group<float, G>(A.C, sh, lane, i, N, on, env_id, action,
+                                                         x, y, th, c, s, gx, gy, step, episode,
+                                                         false);
+      if (i == 0) {
+        A.reward[(size_t)t * A.E + e] = so.reward;
+        A.done[(size_t)t * A.E + e] = so.done ? 1 : 0;
+      }
+    }
+  }
+  if (on) { A.x[r] = x; A.y[r] = y; A.th[r] = th; A.gx[r] = gx; A.gy[r] = gy; }
+  if (env_ok && i == 0) { A.step[e] = step; A.episode[e] = episode; }
+}
+
+static const void *rollout_kernel(int G) {
+  switch (G) {
+    case 2: return reinterpret_cast<const void *>(&k_rollout<2>);
+    case 4: return reinterpret_cast<const void *>(&k_rollout<4>);
+    case 8: return reinterpret_cast<const void *>(&k_rollout<8>);
+    default: return reinterpret_cast<const void *>(&k_rollout<16>);
+  }
+}
+
+static bool launch_rollout(const RolloutArgs &A, dim3 grid, hipStream_t st) {
+  const int G = pow2_group(A.N);
+  switch (G) {
+    case 2: hipLaunchKernelGGL(k_rollout<2>, grid, dim3(kRollBlock), 0, st, A); break;
+    case 4: hipLaunchKernelGGL(k_rollout<4>, grid, dim3(kRollBlock), 0, st, A); break;
+    case 8: hipLaunchKernelGGL(k_rollout<8>, grid, dim3(kRollBlock), 0, st, A); break;
+    default: hipLaunchKernelGGL(k_rollout<16>, grid, dim3(kRollBlock), 0, st, A); break;
+  }
+  return hipGetLastError() == hipSuccess;
+}
+
+}  // namespace rs
+
+using namespace rs;
+
+extern "C" rs_status rollout(rs_ctx *ctx, const rs_params *p, const rs_batch *b,
+                             const rs_policy *policy, int32_t horizon, int64_t t_global0,
+                             float *obs, uint8_t *actions, float *reward, uint8_t *done,
+                             void *stream) {
+  RS_CHECK_ARG(ctx != nullptr, "ctx is NULL");
+  rs_status s = check_params(p);
+  if (s != RS_OK) return s;
+  RS_CHECK_ARG(b != nullptr && policy != nullptr, "batch/policy is NULL");
+  RS_CHECK_ARG(p->dtype == RS_F32, "rollout runs in FP32 (dtype must be RS_F32)");
+  RS_CHECK_ARG(p->controller == RS_CTRL_DISCRETE, "rollout drives the discrete controller");
+  RS_CHECK_ARG(b->num_envs >= 1, "num_envs must be >= 1");
+  RS_CHECK_ARG(b->robots >= 2 && 2 * b->robots + 4 <= 32,
+               "rollout needs 2 <= robots and 2*robots+4 <= 32 (got %d)", b->robots);
+  RS_CHECK_ARG(horizon >= 1, "horizon must be >= 1");
+  RS_CHECK_ARG(policy->in_dim == 2 * b->robots + 4, "policy in_dim %d != 2N+4", policy->in_dim);
+  RS_CHECK_ARG(policy->w1 && policy->w2 && policy->w3 && policy->b1 && policy->b2 && policy->b3,
+               "policy pointer is NULL");
+  RS_CHECK_ARG(actions && reward && done, "actions/reward/done outputs are required");
+  RS_CHECK_ARG(b->x && b->y && b->theta && b->goal_x && b->goal_y && b->step && b->episode,
+               "state pointer is NULL");
+  RS_CHECK_ARG(((uintptr_t)obs & 15) == 0, "obs must be 16-byte aligned");
+  RolloutArgs A;
+  std::memset(&A, 0, sizeof(A));
+  A.C = make_const<float>(*p);
+  A.E = b->num_envs;
+  A.N = b->robots;
+  A.D = 2 * b->robots + 4;
+  A.H = horizon;
+  A.env_base = (uint32_t)b->env_id_base;
+  A.t0 = (uint32_t)t_global0;
+  A.x = (float *)b->x; A.y = (float *)b->y; A.th = (float *)b->theta;
+  A.gx = (float *)b->goal_x; A.gy = (float *)b->goal_y;
+  A.step = b->step; A.episode = b->episode;
+  A.w1 = (const __bf16 *)policy->w1; A.w2 = (const __bf16 *)policy->w2;
+  A.w3 = (const __bf16 *)policy->w3;
+  A.b1 = policy->b1; A.b2 = policy->b2; A.b3 = policy->b3;
+  A.obs = obs; A.actions = actions; A.reward = reward; A.done = done;
+  const int G = pow2_group(A.N);
+  const int waves = (A.E + (64 / G) - 1) / (64 / G);
+  const dim3 grid((waves + kRollWaves - 1) / kRollWaves);
+  hipStream_t st = (hipStream_t)stream;
+
+  // Replay a captured graph of this launch shape; when only scalar arguments
+  // (e.g. the stream time) differ, patch the kernel node of the instantiated
+  // graph instead of capturing again.
+  RolloutArgs shape = A;
+  shape.t0 = 0;
+  GraphKey key;
+  key.words.resize((sizeof(A) + sizeof(uintptr_t) - 1) / sizeof(uintptr_t) + 1, 0);
+  std::memcpy(key.words.data(), &shape, sizeof(shape));
+  key.words.back() = grid.x;
+  auto it = ctx->graphs.find(key);
+  if (it == ctx->graphs.end()) {
+    if (ctx->graphs.size() >= 32) {
+      for (auto &kv : ctx->graphs) {
+        (void)hipGraphExecDestroy(kv.second.exec);
+        (void)hipGraphDestroy(kv.second.graph);
+      }
+      ctx->graphs.clear();
+    }
+    if (!ctx->capture_stream)
+      RS_CHECK_HIP(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+    CachedGraph cg;
+    RS_CHECK_HIP(hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
+    const bool ok = launch_rollout(A, grid, ctx->capture_stream);
+    hipError_t ce = hipStreamEndCapture(ctx->capture_stream, &cg.graph);
+    if (!ok || ce != hipSuccess) {
+      set_error("rollout capture failed: %s", hipGetErrorString(ce));
+      return RS_ERR_DEVICE;
+    }
+    size_t nnodes = 1;
+    hipError_t ne = hipGraphGetNodes(cg.graph, &cg.node, &nnodes);
+    hipError_t ie = hipGraphInstantiate(&cg.exec, cg.graph, nullptr, nullptr, 0);
+    if (ne != hipSuccess || nnodes != 1 || ie != hipSuccess) {
+      set_error("rollout graph instantiate failed: %s", hipGetErrorString(ie));
+      if (cg.graph) (void)hipGraphDestroy(cg.graph);
+      return RS_ERR_DEVICE;
+    }
+    cg.args.assign(reinterpret_cast<const char *>(&A), reinterpret_cast<const char *>(&A) + sizeof(A));
+    it = ctx->graphs.emplace(key, cg).first;
+  } else if (std::memcmp(it->second.args.data(), &A, sizeof(A)) != 0) {
+    RolloutArgs copy = A;
+    void *kargs[] = {&copy};
+    hipKernelNodeParams kp;
+    std::memset(&kp, 0, sizeof(kp));
+    kp.func = const_cast<void *>(rollout_kernel(G));
+    kp.gridDim = grid;
+    kp.blockDim = dim3(kRollBlock);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = kargs;
+    kp.extra = nullptr;
+    RS_CHECK_HIP(hipGraphExecKernelNodeSetParams(it->second.exec, it->second.node, &kp));
+    std::memcpy(it->second.args.data(), &A, sizeof(A));
+  }
+  RS_CHECK_HIP(hipGraphLaunch(it->second.exec, st));
+  return RS_OK;
+}

@@ -1,0 +1,227 @@
+// rs_step.hpp -- one environment step for the lane group that owns the
+// environment (lane i = robot i). Definitions follow robostep.h (JaxRobotarium
+// Sec. 4.1 and the Navigation scenario of the appendix).
+#pragma once
+
+#include "rs_qp.hpp"
+
+namespace rs {
+
+// Discrete single-integrator moves: 0 stay, 1 +x, 2 -x, 3 +y, 4 -y.
+__device__ __forceinline__ void move_dir(int a, int &dx, int &dy) {
+  dx = (a == 1) - (a == 2);
+  dy = (a == 3) - (a == 4);
+}
+
+__device__ __forceinline__ int drawn_action(uint32_t k0, uint32_t k1, uint32_t env_id,
+                                            uint32_t t, int i) {
+  const uint4 o = stream_block(k0, k1, env_id, t, kAction, (uint32_t)(i >> 2), 0u);
+  return (int)(((uint64_t)word(o, i & 3) * 5ull) >> 32);
+}
+
+// Magnitude limit of the nominal command.
+template <typename T>
+__device__ __forceinline__ void preclip(const SimConst<T> &C, T &ux, T &uy) {
+  const T nrm = sqrt_t(ux * ux + uy * uy);
+  if (nrm > C.vmax) {
+    const T sc = C.vmax / nrm;
+    ux *= sc;
+    uy *= sc;
+  }
+}
+
+// Single-integrator command at the projection point -> unicycle (v, w), then
+// GRITSBot wheel-speed saturation.
+template <typename T>
+__device__ __forceinline__ void si_to_uni(const SimConst<T> &C, T c, T s, T ux, T uy, T &v, T &w) {
+  v = c * ux + s * uy;
+  w = (c * uy - s * ux) * C.inv_l;
+  if (C.R > T(0)) {
+    const T halfL = T(0.5) * C.L;
+    T phr = (v + halfL * w) / C.R;
+    T phl = (v - halfL * w) / C.R;
+    phr = tmin(tmax(phr, -C.wheel_lim), C.wheel_lim);
+    phl = tmin(tmax(phl, -C.wheel_lim), C.wheel_lim);
+    v = T(0.5) * C.R * (phr + phl);
+    w = C.R * (phr - phl) / C.L;
+  }
+}
+
+// Explicit Euler with the pre-step heading; heading wrapped to [-pi, pi]
+// (|dt w| < pi, so one correction suffices).
+template <typename T>
+__device__ __forceinline__ void integrate(const SimConst<T> &C, T c, T s, T v, T w, T &x, T &y,
+                                          T &th) {
+  x += C.dt * v * c;
+  y += C.dt * v * s;
+  T t = th + C.dt * w;
+  const T pi = pi_v<T>();
+  if (t > pi) t -= T(2) * pi;
+  else if (t < -pi) t += T(2) * pi;
+  th = t;
+}
+
+// Lattice placement of N points with the minimum separation: every lane of
+// the group draws the same candidate for robot r; lanes j < r test it against
+// their own point; the first candidate nobody rejects is kept by lane r.
+template <typename T, int G>
+__device__ void place_points(const SimConst<T> &C, uint32_t env_id, uint32_t episode,
+                             uint32_t purpose, int i, int N, int lane, int64_t &X, int64_t &Y) {
+  X = 0;
+  Y = 0;
+  for (int r = 0; r < N; ++r) {
+    bool placed = false;
+    for (uint32_t att = 0; att < 64u && !placed; ++att) {
+      const uint4 o = stream_block(C.key0, C.key1, env_id, episode, purpose, (uint32_t)r, att);
+      const int64_t cx = C.xlo + (int64_t)(((uint64_t)o.x * (uint64_t)C.wx) >> 32);
+      const int64_t cy = C.ylo + (int64_t)(((uint64_t)o.y * (uint64_t)C.wy) >> 32);
+      const int64_t ddx = cx - X, ddy = cy - Y;
+      const bool clash = (i < r) && (ddx * ddx + ddy * ddy < C.sep2);
+      if (!group_any<G>(clash, lane)) {
+        placed = true;
+        if (i == r) { X = cx; Y = cy; }
+      }
+    }
+    for (int64_t cy = C.ylo; cy <= C.yhi && !placed; cy += 500) {
+      for (int64_t cx = C.xlo; cx <= C.xhi && !placed; cx += 500) {
+        const int64_t ddx = cx - X, ddy = cy - Y;
+        const bool clash = (i < r) && (ddx * ddx + ddy * ddy < C.sep2);
+        if (!group_any<G>(clash, lane)) {
+          placed = true;
+          if (i == r) { X = cx; Y = cy; }
+        }
+      }
+    }
+    if (!placed && i == r) { X = C.xlo; Y = C.ylo; }
+  }
+}
+
+// Reset sampler for the group's environment (episode `episode`).
+template <typename T, int G>
+__device__ void reset_env(const SimConst<T> &C, uint32_t env_id, uint32_t episode, int i, int N,
+                          int lane, T &x, T &y, T &th, T &gx, T &gy) {
+  int64_t X, Y, GX, GY;
+  place_points<T, G>(C, env_id, episode, kPose, i, N, lane, X, Y);
+  place_points<T, G>(C, env_id, episode, kGoal, i, N, lane, GX, GY);
+  const uint4 hb = stream_block(C.key0, C.key1, env_id, episode, kHeading, (uint32_t)(i >> 2), 0u);
+  const double u = (double)(word(hb, i & 3) >> 8) * 5.9604644775390625e-8;
+  th = (T)(-kPiD + 2.0 * kPiD * u);
+  x = (T)((double)X * C.grid);
+  y = (T)((double)Y * C.grid);
+  gx = (T)((double)GX * C.grid);
+  gy = (T)((double)GY * C.grid);
+}
+
+// Observation of robot i: x, y, cos th, sin th, (x_j - x_i, y_j - y_i) for
+// j != i ascending, g_i - (x_i, y_i). Written to o[0 .. 2N+3].
+template <typename T, int G>
+__device__ __forceinline__ void write_obs(T *o, int lane, int i, int N, bool on, T x, T y, T c,
+                                          T s, T gx, T gy) {
+  const int base = lane & ~(G - 1);
+  if (on) {
+    o[0] = x;
+    o[1] = y;
+    o[2] = c;
+    o[3] = s;
+  }
+  for (int j = 0; j < N; ++j) {
+    const T xj = __shfl(x, base + j, 64), yj = __shfl(y, base + j, 64);
+    if (on && j != i) {
+      const int m = 4 + 2 * (j < i ? j : j - 1);
+      o[m] = xj - x;
+      o[m + 1] = yj - y;
+    }
+  }
+  if (on) {
+    o[2 * N + 2] = gx - x;
+    o[2 * N + 3] = gy - y;
+  }
+}
+
+// Largest normalised violation of (ux, uy) against the rows (owner scan) and
+// bounds; group-uniform result.
+template <typename T, int G>
+__device__ T max_violation(const SimConst<T> &C, int lane, int i, int N, bool on, T px, T py,
+                           T ux, T uy, T lox, T hix, T loy, T hiy) {
+  const int base = lane & ~(G - 1);
+  T worst = T(0);
+  if (on) worst = tmax(tmax(ux - hix, lox - ux), tmax(uy - hiy, loy - uy));
+  for (int k = 1; k <= (N >> 1); ++k) {
+    const int j = on ? (i + k >= N ? i + k - N : i + k) : 0;
+    const T pxj = __shfl(px, base + j, 64), pyj = __shfl(py, base + j, 64);
+    const T uxj = __shfl(ux, base + j, 64), uyj = __shfl(uy, base + j, 64);
+    if (on && !(2 * k == N && i >= k)) {
+      const bool ia = i < j;
+      const T dx = ia ? px - pxj : pxj - px, dy = ia ? py - pyj : pyj - py;
+      const T d2 = dx * dx + dy * dy, h = d2 - C.rs2;
+      const T s = T(2) * (dx * (ia ? uxj - ux : ux - uxj) + dy * (ia ? uyj - uy : uy - uyj)) -
+                  C.gamma * (h * h * h);
+      worst = tmax(worst, d2 > T(0) ? s / (T(2.8284271247461903) * sqrt_t(d2)) : s);
+    }
+  }
+  return tmax(group_max<G>(worst), T(0));
+}
+
+// Result of one group step.
+template <typename T> struct StepOut {
+  T reward;
+  bool done;
+  QPInfo qp;
+  T maxviol;
+};
+
+// One env step for the group (all lanes call together). State (x, y, th,
+// gx, gy, c = cos th, s = sin th) is updated in place; `action` is the lane's
+// discrete action (ignored for the go-to-goal controller). `step`/`episode`
+// are group-uniform and updated. Observation of the post-step state is left
+// to the caller (c, s are refreshed).
+template <typename T, int G>
+__device__ StepOut<T> env_step_group(const SimConst<T> &C, QPScratch<T, G> *sh, int lane, int i,
+                                     int N, bool on, uint32_t env_id, int action, T &x, T &y,
+                                     T &th, T &c, T &s, T &gx, T &gy, int &step, int &episode,
+                                     bool want_viol) {
+  StepOut<T> out;
+  // projection point and nominal command
+  const T px = x + C.l * c, py = y + C.l * s;
+  T unx, uny;
+  if (C.controller == 1) {
+    unx = C.kp * (gx - px);
+    uny = C.kp * (gy - py);
+  } else {
+    int ddx, ddy;
+    move_dir(action, ddx, ddy);
+    unx = C.aspeed * T(ddx);
+    uny = C.aspeed * T(ddy);
+  }
+  preclip(C, unx, uny);
+  T lox, hix, loy, hiy;
+  wall_bounds(C, px, py, lox, hix, loy, hiy);
+  T ux, uy;
+  out.qp = qp_solve<T, G>(sh, C, lane, i, N, on, px, py, unx, uny, lox, hix, loy, hiy, ux, uy);
+  out.maxviol = want_viol ? max_violation<T, G>(C, lane, i, N, on, px, py, ux, uy, lox, hix, loy, hiy)
+                          : T(0);
+  T v, w;
+  si_to_uni(C, c, s, ux, uy, v, w);
+  if (on) integrate(C, c, s, v, w, x, y, th);
+  // reward and termination
+  step += 1;
+  T dist = T(0);
+  if (on) {
+    const T ex = x - gx, ey = y - gy;
+    dist = sqrt_t(ex * ex + ey * ey);
+  }
+  out.reward = -group_sum<G>(dist);
+  const bool near_all = group_all<G>(!on || dist < C.goal_r, lane);
+  out.done = (C.goal_r > T(0) && near_all) || (C.max_steps > 0 && step >= C.max_steps);
+  if (out.done) {
+    episode += 1;
+    step = 0;
+    T nx, ny, nth, ngx, ngy;
+    reset_env<T, G>(C, env_id, (uint32_t)episode, i, N, lane, nx, ny, nth, ngx, ngy);
+    if (on) { x = nx; y = ny; th = nth; gx = ngx; gy = ngy; }
+  }
+  sincos_t(th, &s, &c);
+  return out;
+}
+
+}  // namespace rs

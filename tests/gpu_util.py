@@ -1,0 +1,57 @@
+"""Helpers of the GPU parity tests: device transfers and oracle state views."""
+import math
+import sys
+
+import numpy as np
+
+
+def banner(msg: str):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def ctx_and_lib():
+    import torch
+
+    from paper_2505_06771_amd import robostep as R
+
+    assert torch.cuda.is_available(), "GPU test needs a GPU"
+    R.lib()  # raises if the HIP library is missing
+    return R, R.Context(0)
+
+
+def dev(a, dtype):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype).contiguous()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def batch_from_states(R, st, n, dtype, env_id_base=0, step=None, episode=None):
+    import torch
+
+    E = st["x"].shape[0]
+    b = R.Batch(dev(st["x"].ravel(), dtype), dev(st["y"].ravel(), dtype),
+                dev(st["th"].ravel(), dtype), dev(st["gx"].ravel(), dtype),
+                dev(st["gy"].ravel(), dtype),
+                dev(np.zeros(E, np.int32) if step is None else step, torch.int32),
+                dev(np.zeros(E, np.int32) if episode is None else episode, torch.int32),
+                n, env_id_base)
+    return b
+
+
+def oracle_state(b):
+    """Float64 copies of a device batch for the oracle's batched calls."""
+    return {"x": host(b.x).astype(np.float64), "y": host(b.y).astype(np.float64),
+            "th": host(b.theta).astype(np.float64), "gx": host(b.goal_x).astype(np.float64),
+            "gy": host(b.goal_y).astype(np.float64),
+            "step": host(b.step).astype(np.int32).copy(),
+            "episode": host(b.episode).astype(np.int32).copy()}
+
+
+def angle_diff(a, b):
+    d = np.asarray(a, np.float64) - np.asarray(b, np.float64)
+    return np.abs((d + math.pi) % (2 * math.pi) - math.pi)

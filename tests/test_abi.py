@@ -1,0 +1,100 @@
+"""CPU checks of the C ABI: the HIP library loads, exports every function that
+include/robostep.h declares, and its host-only calls behave (defaults, status
+strings, request sizing, argument validation before any device work)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "robostep.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s+\**([A-Za-z_][A-Za-z0-9_]*)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "return")))
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_2505_06771_amd import robostep
+
+    if not os.path.exists(robostep.LIB_PATH):
+        from paper_2505_06771_amd import build
+
+        build.build()
+    robostep.lib()
+    return robostep
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("env_reset", "env_step", "barrier_certificate", "rollout", "env_run",
+              "rs_create", "rs_server_submit", "rs_autotune"):
+        assert n in names
+    assert len(names) >= 25
+
+
+def test_every_declared_symbol_is_exported(R):
+    L = R.lib()
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, f"not exported: {missing}"
+
+
+def test_params_default_match_the_configuration(R):
+    p = R.params()
+    assert (p.x_min, p.x_max, p.y_min, p.y_max) == (-1.6, 1.6, -1.0, 1.0)
+    assert p.dt == 0.033 and p.proj_dist == 0.05 and p.barrier_gain == 100.0
+    assert p.safety_radius == 0.17 and p.v_max == 0.2 and p.max_steps == 500
+    assert p.goal_radius == 0.05 and p.dtype == R.RS_F32
+
+
+def test_params_struct_matches_oracle_constants(R):
+    import oracle
+
+    o = oracle.Params()
+    p = R.params()
+    for f in ("x_min", "x_max", "dt", "proj_dist", "barrier_gain", "safety_radius",
+              "boundary_gain_factor", "v_max", "action_speed", "kp", "wheel_radius",
+              "base_length", "goal_radius", "reset_margin", "min_sep", "grid", "max_steps"):
+        assert getattr(o, f) == getattr(p, f), f
+
+
+def test_status_strings(R):
+    L = R.lib()
+    assert L.rs_status_string(0) == b"ok"
+    assert L.rs_status_string(5) == b"over budget"
+
+
+def test_request_bytes(R):
+    L = R.lib()
+    assert L.rs_request_bytes(0, 4) == 0
+    b = L.rs_request_bytes(100, 8)
+    assert b >= 100 * 8 * 20 and b % 256 == 0
+
+
+def test_null_arguments_are_rejected_without_device_work(R):
+    L = R.lib()
+    p = R.params()
+    st = L.env_step(None, ctypes.byref(p), None, None, 0, None, None, None, None, None, None)
+    assert st == 1
+    assert b"NULL" in L.rs_last_error()
+    st = L.barrier_certificate(None, ctypes.byref(p), 4, 4, None, None, None, None, None, None,
+                               None, None, None, None)
+    assert st == 1
+    out = ctypes.c_void_p()
+    st = L.rs_plan_create(None, 4, None, None, ctypes.byref(out))
+    assert st == 1
+
+
+def test_gpu_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    from paper_2505_06771_amd import robostep
+
+    monkeypatch.setattr(robostep, "_lib", None)
+    monkeypatch.setattr(robostep, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        robostep.lib()

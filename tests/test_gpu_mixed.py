@@ -1,0 +1,161 @@
+"""GPU tests of mixed-size batches: env_reset_mixed, env_run (one persistent
+launch over envs with different robot counts), schedule independence and the
+autotuner.
+
+Parity: one env_run step is compared with the FP64 oracle teacher-forced
+(tolerances as in test_gpu_step); a k-step env_run equals k one-step launches
+bit for bit; results are identical under every schedule (lanes per env,
+block size) and for an env alone or inside a mixed batch.
+"""
+import numpy as np
+import pytest
+
+from paper_2505_06771_amd import synth
+from tests.gpu_util import angle_diff, banner, ctx_and_lib, dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+def _mixed_batch(R, ctx, counts, seed, env_id_base=0, schedule=None):
+    import torch
+
+    plan = R.Plan(ctx, counts, schedule)
+    b = R.Batch.empty(len(counts), 0, env_id_base=env_id_base, total_robots=plan.total_robots)
+    b.robots = 0
+    R.env_reset_mixed(ctx, R.params(seed=seed), plan, b)
+    return plan, b
+
+
+def _offsets(counts):
+    return np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+
+
+def test_reset_mixed_matches_oracle(orc):
+    import torch
+
+    R, ctx = ctx_and_lib()
+    counts = synth.uneven_sizes(1, 157)
+    banner("reset mixed")
+    plan, b = _mixed_batch(R, ctx, counts, seed=4, env_id_base=10)
+    torch.cuda.synchronize()
+    off = _offsets(counts)
+    x, th = host(b.x), host(b.theta)
+    po = orc.Params(seed=4)
+    for e, n in enumerate(counts):
+        ox, oy, oth, ogx, ogy = orc.reset_env(po, 10 + e, 0, int(n))
+        np.testing.assert_array_equal(x[off[e]:off[e + 1]], ox.astype(np.float32))
+        assert angle_diff(th[off[e]:off[e + 1]], oth).max() <= 1e-6
+
+
+def test_env_run_one_step_teacher_forced(orc):
+    import torch
+
+    R, ctx = ctx_and_lib()
+    counts = synth.uneven_sizes(2, 211)
+    E = len(counts)
+    plan, b = _mixed_batch(R, ctx, counts, seed=6)
+    # push the step counters near the time limit so resets happen
+    b.step.copy_(torch.from_numpy(np.random.default_rng(0).integers(490, 500, E).astype(np.int32)).cuda())
+    off = _offsets(counts)
+    po = orc.Params(seed=6)
+    p = R.params(seed=6)
+    rew = torch.zeros(E, device="cuda")
+    done = torch.zeros(E, dtype=torch.uint8, device="cuda")
+    total_obs = sum(int(n) * (2 * int(n) + 4) for n in counts)
+    obs = torch.zeros(total_obs, device="cuda")
+    banner("env_run teacher forced")
+    resets = 0
+    for t in range(15):
+        before = {k: host(getattr(b, a)).astype(np.float64) for k, a in
+                  (("x", "x"), ("y", "y"), ("th", "theta"), ("gx", "goal_x"), ("gy", "goal_y"))}
+        st0, ep0 = host(b.step).copy(), host(b.episode).copy()
+        R.env_run(ctx, p, plan, b, 1, t_global0=300 + t, reward_out=rew, done_out=done,
+                  obs_final=obs)
+        torch.cuda.synchronize()
+        gx_, gy_, gth = host(b.x), host(b.y), host(b.theta)
+        gob, grw, gdn = host(obs), host(rew), host(done)
+        for e, n in enumerate(counts):
+            n = int(n)
+            sl = slice(off[e], off[e + 1])
+            one = {k: v[sl].copy() for k, v in before.items()}
+            one["step"], one["episode"] = int(st0[e]), int(ep0[e])
+            out = orc.env_step(po, one, e, 300 + t)
+            assert out["status"] != 2
+            assert out["done"] == gdn[e]
+            resets += out["done"]
+            assert np.abs(one["x"] - gx_[sl]).max() <= 1e-5
+            assert np.abs(one["y"] - gy_[sl]).max() <= 1e-5
+            assert angle_diff(one["th"], gth[sl]).max() <= 6.6e-5
+            assert abs(out["reward"] - grw[e]) <= n * 1e-5
+            o0 = plan.obs_offset(e)
+            np.testing.assert_allclose(gob[o0:o0 + n * (2 * n + 4)].reshape(n, 2 * n + 4),
+                                       out["obs"], atol=1e-5, rtol=0)
+    assert resets > E // 2
+
+
+def _run_steps(R, ctx, counts, seed, steps, schedule=None, chunks=1, env_id_base=0):
+    import torch
+
+    plan, b = _mixed_batch(R, ctx, counts, seed, env_id_base=env_id_base, schedule=schedule)
+    p = R.params(seed=seed)
+    E = len(counts)
+    rsum = torch.zeros(E, device="cuda")
+    per = steps // chunks
+    for k in range(chunks):
+        R.env_run(ctx, p, plan, b, per, t_global0=k * per, reward_sum=rsum)
+    torch.cuda.synchronize()
+    return host(b.x).copy(), host(b.theta).copy(), host(rsum).copy(), plan
+
+
+def test_multi_step_equals_single_steps():
+    R, ctx = ctx_and_lib()
+    counts = synth.uneven_sizes(3, 300)
+    banner("env_run chunking")
+    a = _run_steps(R, ctx, counts, 9, 40, chunks=1)
+    b = _run_steps(R, ctx, counts, 9, 40, chunks=40)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+    np.testing.assert_allclose(a[2], b[2], rtol=1e-6, atol=1e-5)  # summation order differs
+
+
+def test_schedule_independence():
+    R, ctx = ctx_and_lib()
+    counts = synth.uneven_sizes(4, 260)
+    banner("schedules")
+    ref = _run_steps(R, ctx, counts, 12, 25)
+    for blk, wide in [(64, False), (128, True), (256, True)]:
+        s = R.RsSchedule()
+        s.block_threads = blk
+        for n in range(2, 17):
+            g = 2
+            while g < n:
+                g *= 2
+            s.lanes_per_env[n] = min(16, 2 * g) if wide else g
+        got = _run_steps(R, ctx, counts, 12, 25, schedule=s)
+        np.testing.assert_array_equal(got[0], ref[0])
+        np.testing.assert_array_equal(got[1], ref[1])
+        np.testing.assert_array_equal(got[2], ref[2])
+
+
+def test_env_alone_equals_env_in_mix():
+    R, ctx = ctx_and_lib()
+    mix = synth.uneven_sizes(5, 120)
+    # last 20 envs have 8 robots: run them alone with the same env ids
+    counts = np.concatenate([mix, np.full(20, 8, np.int32)])
+    banner("alone vs mix")
+    a = _run_steps(R, ctx, counts, 21, 30)
+    alone = _run_steps(R, ctx, np.full(20, 8, np.int32), 21, 30, env_id_base=len(mix))
+    off = int(np.sum(mix))
+    np.testing.assert_array_equal(a[0][off:], alone[0])
+    np.testing.assert_array_equal(a[2][len(mix):], alone[2])
+
+
+def test_autotune_returns_valid_schedule():
+    R, ctx = ctx_and_lib()
+    banner("autotune")
+    s = R.autotune(ctx, R.params(), [4, 8], envs=512, steps=20, tol=1e-4)
+    for n in (4, 8):
+        g = s.lanes_per_env[n]
+        assert g >= n and g in (4, 8, 16)
+        assert s.qp_iters[n] in (2 * n + 4, 4 * n + 8, 8 * n + 32)
+    assert s.block_threads in (64, 128, 256)

@@ -1,0 +1,202 @@
+"""GPU parity of the fused rollout (MFMA bf16 policy, sampling, env step)
+against the FP64 oracle, teacher-forced from the GPU's own observations.
+
+For every step t the oracle (1) evaluates the policy on the GPU's obs_t
+(bf16-rounded, FP64 sums) and draws the action with the same counter-based
+uniform, and (2) steps the state reconstructed from obs_t with the GPU's
+action; the result must reproduce obs_{t+1}, reward_t and done_t.
+
+Decisions taken in floating point: an action may differ only where the
+oracle's uniform lies within 2e-3 of a CDF boundary (the FP32 accumulation on
+the GPU can round a hidden activation to the neighbouring bfloat16, which
+moves a logit by ~1e-3); such cases must stay below 0.5% of the draws. Done
+flags follow the 1e-5 m band of the env_step tests.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2505_06771_amd import synth
+from tests.gpu_util import angle_diff, banner, batch_from_states, ctx_and_lib, dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+def _policy(R, torch, w):
+    bf = lambda a: torch.from_numpy(a).to(torch.bfloat16).cuda().contiguous()
+    fl = lambda a: torch.from_numpy(a).float().cuda().contiguous()
+    return R.Policy(bf(w["w1"]), fl(w["b1"]), bf(w["w2"]), fl(w["b2"]), bf(w["w3"]), fl(w["b3"]))
+
+
+def _state_from_obs(ob, n):
+    """ob [E, n, 2n+4] -> oracle state arrays [E*n]."""
+    x, y = ob[..., 0], ob[..., 1]
+    th = np.arctan2(ob[..., 3], ob[..., 2])
+    gx, gy = x + ob[..., 2 * n + 2], y + ob[..., 2 * n + 3]
+    return {k: np.ascontiguousarray(v.reshape(-1), np.float64)
+            for k, v in (("x", x), ("y", y), ("th", th), ("gx", gx), ("gy", gy))}
+
+
+def _cdf_margin(logits, u):
+    pr = np.exp(logits - logits.max())
+    pr /= pr.sum()
+    return np.abs(np.cumsum(pr)[:4] - u).min()
+
+
+def run_and_check(orc, n, E, H, seed, sample_envs=None, sample_steps=None, step0=None):
+    import torch
+
+    R, ctx = ctx_and_lib()
+    dim = 2 * n + 4
+    st = synth.random_states(seed, E, n) if E <= 4096 else None
+    if st is None:
+        b = R.Batch.empty(E, n, env_id_base=0)
+        R.env_reset(ctx, R.params(seed=seed), b)
+    else:
+        b = batch_from_states(R, st, n, torch.float32, env_id_base=0,
+                              step=step0 if step0 is not None else None)
+    w = synth.policy_weights(seed, dim, bias_scale=0.1)
+    pol = _policy(R, torch, w)
+    obs = torch.zeros(H * E * n * dim, device="cuda")
+    act = torch.zeros(H * E * n, dtype=torch.uint8, device="cuda")
+    rew = torch.zeros(H * E, device="cuda")
+    done = torch.zeros(H * E, dtype=torch.uint8, device="cuda")
+    step_init = host(b.step).astype(np.int32).copy()
+    ep_init = host(b.episode).astype(np.int32).copy()
+    p = R.params(seed=seed)
+    po = orc.Params(seed=seed)
+    t0 = 1000
+    banner(f"rollout n={n} E={E} H={H}")
+    R.rollout(ctx, p, b, pol, H, t0, obs, act, rew, done)
+    torch.cuda.synchronize()
+    ob = host(obs).reshape(H, E, n, dim).astype(np.float64)
+    ac = host(act).reshape(H, E, n)
+    rw = host(rew).reshape(H, E)
+    dn = host(done).reshape(H, E)
+    wd = {k: v.astype(np.float64) for k, v in w.items()}
+    envs = np.arange(E) if sample_envs is None else np.asarray(sample_envs)
+    steps = range(H) if sample_steps is None else sample_steps
+    # counters along the GPU trajectory
+    stepc = np.zeros((H + 1, E), np.int32)
+    epc = np.zeros((H + 1, E), np.int32)
+    stepc[0], epc[0] = step_init, ep_init
+    for t in range(H):
+        stepc[t + 1] = np.where(dn[t] == 1, 0, stepc[t] + 1)
+        epc[t + 1] = epc[t] + dn[t]
+    nact, nband, worst = 0, 0, 0.0
+    for t in steps:
+        for e in envs:
+            for i in range(n):
+                lg = orc.policy_logits(wd, ob[t, e, i])
+                bits = orc.policy_bits(po, int(e), t0 + t, i)
+                a = orc.sample_action(lg, bits)
+                nact += 1
+                if a != ac[t, e, i]:
+                    u = (bits >> 8) * 2.0 ** -24
+                    m = _cdf_margin(lg, u)
+                    assert m < 2e-3, f"t={t} e={e} i={i}: action {ac[t, e, i]} vs {a}, margin {m}"
+                    nband += 1
+        if t + 1 >= H:
+            continue
+        sub = ob[t][envs]
+        s = _state_from_obs(sub, n)
+        s["step"] = stepc[t][envs].copy()
+        s["episode"] = epc[t][envs].copy()
+        acts = np.ascontiguousarray(ac[t][envs].reshape(-1))
+        # the oracle batch keys the stream by env_id_base + position: step env by env
+        for k, e in enumerate(envs):
+            one = {kk: s[kk][k * n:(k + 1) * n].copy() for kk in ("x", "y", "th", "gx", "gy")}
+            one["step"], one["episode"] = int(s["step"][k]), int(s["episode"][k])
+            out = orc.env_step(po, one, int(e), t0 + t, actions=acts[k * n:(k + 1) * n])
+            assert out["status"] != 2
+            if out["done"] != dn[t, e]:
+                # band: some robot within 1e-5 m of the goal radius
+                free = {kk: s[kk][k * n:(k + 1) * n].copy() for kk in ("x", "y", "th", "gx", "gy")}
+                free["step"], free["episode"] = 0, 0
+                pf = orc.Params(**{**po.__dict__, "goal_radius": 0.0, "max_steps": 0})
+                orc.env_step(pf, free, int(e), t0 + t, actions=acts[k * n:(k + 1) * n])
+                dist = np.hypot(free["x"] - free["gx"], free["y"] - free["gy"])
+                assert (np.abs(dist - po.goal_radius) < 1e-5).any(), f"done t={t} e={e}"
+                continue
+            nxt = ob[t + 1, e]
+            d = max(np.abs(one["x"] - nxt[:, 0]).max(), np.abs(one["y"] - nxt[:, 1]).max())
+            worst = max(worst, d)
+            assert d <= 1e-5, f"t={t} e={e}: pose gap {d}"
+            assert abs(out["reward"] - rw[t, e]) <= n * 1e-5
+            np.testing.assert_allclose(out["obs"], nxt, atol=1e-5, rtol=0)
+    print(f"rollout n={n}: actions {nact}, band mismatches {nband}, worst pose gap {worst:.3g}")
+    assert nband <= max(2, 0.005 * nact)
+    return b, ob, ac, rw, dn
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 6, 8, 14])
+def test_rollout_teacher_forced(orc, n):
+    E = {2: 101, 3: 70, 4: 67, 6: 53, 8: 203, 14: 29}[n]
+    rng = np.random.default_rng(n)
+    step0 = rng.integers(470, 500, E).astype(np.int32)  # crosses the 500-step reset
+    run_and_check(orc, n, E, H=40, seed=20 + n, step0=step0)
+
+
+def test_rollout_full_size_sampled(orc):
+    """The benchmarked shape: 16384 envs x 8 robots, 128 steps, sampled envs."""
+    E, n, H = 16384, 8, 128
+    rng = np.random.default_rng(0)
+    envs = np.sort(rng.choice(E, 24, replace=False))
+    envs = np.concatenate([envs, [0, E - 1]])
+    run_and_check(orc, n, E, H, seed=0, sample_envs=envs, sample_steps=[0, 1, 63, 126, 127])
+
+
+def test_rollout_graph_replay_is_deterministic(orc):
+    import torch
+
+    R, ctx = ctx_and_lib()
+    n, E, H = 8, 300, 16
+    dim = 2 * n + 4
+    st = synth.random_states(5, E, n)
+    w = synth.policy_weights(5, dim)
+    pol = _policy(R, torch, w)
+    outs = []
+    banner("rollout replay")
+    for rep in range(3):
+        b = batch_from_states(R, st, n, torch.float32)
+        obs = torch.zeros(H * E * n * dim, device="cuda")
+        act = torch.zeros(H * E * n, dtype=torch.uint8, device="cuda")
+        rew = torch.zeros(H * E, device="cuda")
+        done = torch.zeros(H * E, dtype=torch.uint8, device="cuda")
+        R.rollout(ctx, R.params(seed=5), b, pol, H, 0, obs, act, rew, done)
+        torch.cuda.synchronize()
+        outs.append((host(obs).copy(), host(act).copy(), host(b.x).copy()))
+    for o in outs[1:]:
+        for u, v in zip(o, outs[0]):
+            np.testing.assert_array_equal(u, v)
+
+
+def test_rollout_matches_env_step_chain(orc):
+    """rollout's env part equals env_step driven with the rollout's actions."""
+    import torch
+
+    R, ctx = ctx_and_lib()
+    n, E, H = 6, 90, 12
+    dim = 2 * n + 4
+    st = synth.random_states(8, E, n)
+    w = synth.policy_weights(8, dim)
+    pol = _policy(R, torch, w)
+    b1 = batch_from_states(R, st, n, torch.float32)
+    obs = torch.zeros(H * E * n * dim, device="cuda")
+    act = torch.zeros(H * E * n, dtype=torch.uint8, device="cuda")
+    rew = torch.zeros(H * E, device="cuda")
+    done = torch.zeros(H * E, dtype=torch.uint8, device="cuda")
+    banner("rollout vs env_step chain")
+    R.rollout(ctx, R.params(seed=8), b1, pol, H, 50, obs, act, rew, done)
+    b2 = batch_from_states(R, st, n, torch.float32)
+    o2 = torch.zeros(E * n * dim, device="cuda")
+    r2 = torch.zeros(E, device="cuda")
+    for t in range(H):
+        a = act[t * E * n:(t + 1) * E * n].contiguous()
+        R.env_step(ctx, R.params(seed=8), b2, actions=a, t_global=50 + t, obs=o2, reward=r2)
+        if t + 1 < H:
+            np.testing.assert_allclose(host(o2), host(obs)[(t + 1) * E * n * dim:(t + 2) * E * n * dim],
+                                       atol=2e-6, rtol=0)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(host(b1.x), host(b2.x), atol=2e-6, rtol=0)
