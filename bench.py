@@ -166,9 +166,11 @@ def main():
     ap.add_argument("--robots", type=int, default=8)
     ap.add_argument("--horizon", type=int, default=128)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--cpu-envs", type=int, default=256)
+    ap.add_argument("--cpu-envs", type=int, default=2048)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--suite", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--suite-out", default=os.path.join(ROOT, "gpurun_out", "bench_suite.json"))
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -183,6 +185,13 @@ def main():
 
     R.lib()  # raises if the HIP library is not built
     res = bench_rollout(args)
+    if args.calib_copy:
+        src = torch.ones(1 << 28, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: 3 x 1 GiB device-to-device")
     if args.suite:
         from paper_2505_06771_amd import bench_suite
 

@@ -1,0 +1,301 @@
+"""Secondary benchmarks of the batched Robotarium step (one MI355X).
+
+  single_env_f64   1 env x 4 robots, go-to-goal, FP64, 1000 steps: per-step
+                   env_step launches, plain and hipGraph-captured (us/step)
+  uniform_4096x4   4096 envs x 4 robots, random moves, 1000 steps: per-step
+                   env_step launches (plain, graph) and one persistent env_run
+  uneven_8192      8192 envs, N in {2,4,6,8,12} (0.1/0.3/0.3/0.2/0.1), 1000
+                   steps: one persistent env_run launch (default and autotuned
+                   schedule) vs per-size env_step launches (5 per step)
+  serving          Poisson rollout requests (64-4096 envs log-uniform, N in
+                   3..16, horizon 50-500): continuous batching vs plain
+                   per-request per-step launches; p50/p99 latency + robot-steps/s
+
+Every number is measured with inputs resident on the device; results are
+written as JSON lines to the output file and echoed on stderr.
+"""
+from __future__ import annotations
+
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _sync():
+    import torch
+
+    torch.cuda.synchronize()
+
+
+def _graph_of(fn):
+    """Capture fn() (a sequence of library launches on the current stream)."""
+    import torch
+
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        fn()  # warm-up outside capture
+    torch.cuda.current_stream().wait_stream(s)
+    _sync()
+    with torch.cuda.graph(g):
+        fn()
+    _sync()
+    return g
+
+
+def launch_floor_us(reps=2000):
+    import torch
+
+    torch.cuda._sleep(1)
+    _sync()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        torch.cuda._sleep(1)
+    _sync()
+    return (time.perf_counter() - t0) / reps * 1e6
+
+
+def single_env_f64(R, ctx, seed=0, steps=1000):
+    import torch
+
+    p = R.params(controller=R.RS_CTRL_GOTO, goal_radius=0.0, max_steps=0, dtype=R.RS_F64,
+                 seed=seed)
+    b = R.Batch.empty(1, 4, dtype=torch.float64)
+    R.env_reset(ctx, p, b)
+    _sync()
+    t0 = time.perf_counter()
+    for t in range(steps):
+        R.env_step(ctx, p, b, t_global=t)
+    _sync()
+    plain = (time.perf_counter() - t0) / steps * 1e6
+    g = _graph_of(lambda: [R.env_step(ctx, p, b, t_global=t) for t in range(100)])
+    t0 = time.perf_counter()
+    for _ in range(steps // 100):
+        g.replay()
+    _sync()
+    graph = (time.perf_counter() - t0) / steps * 1e6
+    return {"config": "single_env_f64", "envs": 1, "robots": 4, "steps": steps,
+            "us_per_step_plain": plain, "us_per_step_graph": graph,
+            "robot_steps_per_s_graph": 4 / (graph * 1e-6)}
+
+
+def uniform_4096x4(R, ctx, seed=0, steps=1000):
+    import torch
+
+    E, n = 4096, 4
+    p = R.params(seed=seed)
+    b = R.Batch.empty(E, n)
+    R.env_reset(ctx, p, b)
+    obs = torch.empty(E * n * (2 * n + 4), device="cuda")
+    rew = torch.empty(E, device="cuda")
+    done = torch.empty(E, dtype=torch.uint8, device="cuda")
+    step = lambda t: R.env_step(ctx, p, b, t_global=t, obs=obs, reward=rew, done=done)
+    step(0)
+    _sync()
+    t0 = time.perf_counter()
+    for t in range(steps):
+        step(t)
+    _sync()
+    plain = (time.perf_counter() - t0) / steps
+    g = _graph_of(lambda: [step(t) for t in range(100)])
+    t0 = time.perf_counter()
+    for _ in range(steps // 100):
+        g.replay()
+    _sync()
+    graph = (time.perf_counter() - t0) / steps
+    plan = R.Plan(ctx, np.full(E, n, np.int32))
+    R.env_run(ctx, p, plan, b, 10)
+    _sync()
+    t0 = time.perf_counter()
+    R.env_run(ctx, p, plan, b, steps, t_global0=0)
+    _sync()
+    persist = (time.perf_counter() - t0) / steps
+    rs = E * n
+    return {"config": "uniform_4096x4", "envs": E, "robots": n, "steps": steps,
+            "us_per_step_plain": plain * 1e6, "us_per_step_graph": graph * 1e6,
+            "us_per_step_env_run": persist * 1e6, "launch_floor_us": launch_floor_us(),
+            "robot_steps_per_s_plain": rs / plain, "robot_steps_per_s_graph": rs / graph,
+            "robot_steps_per_s_env_run": rs / persist}
+
+
+def uneven_8192(R, ctx, seed=0, steps=1000, autotune=True):
+    import torch
+
+    from paper_2505_06771_amd import synth
+
+    counts = synth.uneven_sizes(seed, 8192)
+    robots = int(counts.sum())
+    p = R.params(seed=seed)
+    out = {"config": "uneven_8192", "envs": 8192, "robots_total": robots, "steps": steps}
+
+    def persistent(schedule, label):
+        plan = R.Plan(ctx, counts, schedule)
+        b = R.Batch.empty(8192, 0, total_robots=plan.total_robots)
+        R.env_reset_mixed(ctx, p, plan, b)
+        R.env_run(ctx, p, plan, b, 5)
+        _sync()
+        t0 = time.perf_counter()
+        R.env_run(ctx, p, plan, b, steps, t_global0=0)
+        _sync()
+        dt = time.perf_counter() - t0
+        out[f"robot_steps_per_s_{label}"] = robots * steps / dt
+        out[f"ms_{label}"] = dt * 1e3
+
+    persistent(None, "persistent_default")
+    if autotune:
+        t0 = time.perf_counter()
+        s = R.autotune(ctx, p, [2, 4, 6, 8, 12], envs=2048, steps=50, tol=1e-4)
+        out["autotune_s"] = time.perf_counter() - t0
+        out["schedule"] = {"block_threads": s.block_threads,
+                           "lanes_per_env": {n: s.lanes_per_env[n] for n in (2, 4, 6, 8, 12)},
+                           "qp_iters": {n: s.qp_iters[n] for n in (2, 4, 6, 8, 12)}}
+        persistent(s, "persistent_autotuned")
+    # plain: one uniform batch per size, 5 env_step launches per step
+    batches = []
+    base = 0
+    for n in sorted(set(counts.tolist())):
+        k = int((counts == n).sum())
+        bb = R.Batch.empty(k, n, env_id_base=base)
+        R.env_reset(ctx, p, bb)
+        batches.append(bb)
+        base += k
+    for bb in batches:
+        R.env_step(ctx, p, bb, t_global=0)
+    _sync()
+    t0 = time.perf_counter()
+    for t in range(steps):
+        for bb in batches:
+            R.env_step(ctx, p, bb, t_global=t)
+    _sync()
+    dt = time.perf_counter() - t0
+    out["robot_steps_per_s_plain_per_size"] = robots * steps / dt
+    out["ms_plain_per_size"] = dt * 1e3
+    return out
+
+
+def serving(R, ctx, seed=0, count=600, skip=60, budget=16 << 30, tick=32, rate=None,
+            plain_count=120):
+    """Continuous batching vs plain per-request launches on the same Poisson
+    arrival process. `rate` defaults to 0.7 x the saturated capacity of the
+    served path (measured first on a burst) / mean request work."""
+    import torch
+
+    from paper_2505_06771_amd import synth
+
+    p = R.params(seed=seed)
+    probe = synth.request_stream(seed + 1, 64, 1.0)
+    # saturated capacity: all requests at once
+    srv = R.Server(ctx, p, budget, tick)
+    t0 = time.perf_counter()
+    for r in probe:
+        srv.submit(r["id"], r["envs"], r["robots"], r["horizon"])
+    while srv.tick():
+        while srv.poll() is not None:
+            pass
+    while srv.poll() is not None:
+        pass
+    cap = srv.stats().robot_steps / (time.perf_counter() - t0)
+    srv.close()
+    mean_work = np.mean([r["envs"] * r["robots"] * r["horizon"] for r in probe])
+    if rate is None:
+        rate = 0.7 * cap / mean_work
+    reqs = synth.request_stream(seed, count, rate)
+
+    def run_served():
+        srv = R.Server(ctx, p, budget, tick)
+        lat, late = {}, {}
+        start = time.perf_counter()
+        k = 0
+        while len(lat) < count:
+            now = time.perf_counter() - start
+            while k < count and reqs[k]["arrival"] <= now:
+                r = reqs[k]
+                srv.submit(r["id"], r["envs"], r["robots"], r["horizon"])
+                late[r["id"]] = (time.perf_counter() - start) - r["arrival"]
+                k += 1
+            busy = srv.tick()
+            while True:
+                info = srv.poll()
+                if info is None:
+                    break
+                # completion - arrival: server clock from submission to
+                # completion plus the driver's own delay in submitting
+                lat[info.id] = (info.finish_time - info.submit_time) + late[info.id]
+            if not busy and k < count:
+                time.sleep(max(0.0, min(1e-3, reqs[k]["arrival"] - (time.perf_counter() - start))))
+        wall = time.perf_counter() - start
+        st = srv.stats()
+        srv.close()
+        return lat, wall, st.robot_steps
+
+    def run_plain(n_req):
+        """FIFO, one request at a time, reset + one env_step launch per step."""
+        lat = {}
+        start = time.perf_counter()
+        work = 0
+        for r in reqs[:n_req]:
+            now = time.perf_counter() - start
+            if now < r["arrival"]:
+                time.sleep(r["arrival"] - now)
+            b = R.Batch.empty(r["envs"], r["robots"], env_id_base=r["id"] << 20)
+            R.env_reset(ctx, p, b)
+            for t in range(r["horizon"]):
+                R.env_step(ctx, p, b, t_global=t)
+            _sync()
+            lat[r["id"]] = time.perf_counter() - start - r["arrival"]
+            work += r["envs"] * r["robots"] * r["horizon"]
+        return lat, time.perf_counter() - start, work
+
+    lat_s, wall_s, work_s = run_served()
+    ls = np.array([lat_s[i] for i in range(skip, count)])
+    n_plain = min(plain_count, count)
+    lat_p, wall_p, work_p = run_plain(n_plain)
+    lp = np.array([lat_p[i] for i in range(min(skip, n_plain // 2), n_plain)])
+    return {"config": "serving", "requests": count, "excluded_warmup": skip,
+            "arrival_rate_hz": rate, "saturated_capacity_robot_steps_per_s": cap,
+            "mean_request_robot_steps": mean_work, "tick_steps": tick, "budget_bytes": budget,
+            "served_p50_ms": float(np.percentile(ls, 50) * 1e3),
+            "served_p99_ms": float(np.percentile(ls, 99) * 1e3),
+            "served_robot_steps_per_s": work_s / wall_s,
+            "plain_requests": n_plain,
+            "plain_p50_ms": float(np.percentile(lp, 50) * 1e3),
+            "plain_p99_ms": float(np.percentile(lp, 99) * 1e3),
+            "plain_robot_steps_per_s": work_p / wall_p}
+
+
+def run_all(path, seed=0, which=("single_env_f64", "uniform_4096x4", "uneven_8192", "serving")):
+    import os
+
+    from paper_2505_06771_amd import robostep as R
+
+    ctx = R.Context(0)
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    fns = {"single_env_f64": single_env_f64, "uniform_4096x4": uniform_4096x4,
+           "uneven_8192": uneven_8192, "serving": serving}
+    with open(path, "w") as f:
+        for name in which:
+            _log(f"[suite] {name} ...")
+            res = fns[name](R, ctx, seed=seed)
+            _log(f"[suite] {json.dumps(res)}")
+            f.write(json.dumps(res) + "\n")
+            f.flush()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    import argparse
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default="gpurun_out/bench_suite.json")
+    ap.add_argument("--only", nargs="*")
+    a = ap.parse_args()
+    run_all(a.out, which=tuple(a.only) if a.only else
+            ("single_env_f64", "uniform_4096x4", "uneven_8192", "serving"))

@@ -24,6 +24,8 @@ __device__ __forceinline__ void sincos_t(float a, float *s, float *c) { sincosf(
 __device__ __forceinline__ void sincos_t(double a, double *s, double *c) { sincos(a, s, c); }
 __device__ __forceinline__ float sqrt_t(float a) { return sqrtf(a); }
 __device__ __forceinline__ double sqrt_t(double a) { return sqrt(a); }
+__device__ __forceinline__ float rsqrt_t(float a) { return rsqrtf(a); }
+__device__ __forceinline__ double rsqrt_t(double a) { return rsqrt(a); }
 
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32 multiplies
 // with a Weyl key schedule.
@@ -120,6 +122,7 @@ template <typename T> struct SimConst {
   T x_min, x_max, y_min, y_max;
   T dt, l, inv_l, gamma, rs2, kb, half, vmax, aspeed, kp;
   T R, L, wheel_lim;  // R <= 0: no saturation
+  T inv_R, R_over_L;  // 1/R and R/L
   T goal_r;
   T tol_add;          // active-set admission threshold (normalised violation)
   T eps_z;            // relative threshold for a dependent constraint

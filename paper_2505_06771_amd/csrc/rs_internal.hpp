@@ -102,6 +102,8 @@ template <typename T> SimConst<T> make_const(const rs_params &p) {
   C.R = sat ? (T)p.wheel_radius : T(0);
   C.L = sat ? (T)p.base_length : T(1);
   C.wheel_lim = sat ? (T)(p.v_max / p.wheel_radius) : T(0);
+  C.inv_R = sat ? (T)(1.0 / p.wheel_radius) : T(0);
+  C.R_over_L = sat ? (T)(p.wheel_radius / p.base_length) : T(0);
   C.goal_r = (T)p.goal_radius;
   const bool f32 = sizeof(T) == 4;
   C.tol_add = f32 ? (T)2e-6 : (T)1e-12;

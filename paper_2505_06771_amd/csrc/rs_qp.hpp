@@ -177,7 +177,7 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, const SimConst<T> &C, int lane, 
           const T duy = ia ? uyj - uy : uy - uyj;
           const T s = T(2) * (dx * dux + dy * duy) - bb;
           if (d2 > T(0)) {
-            const T sn = s / (T(2.8284271247461903) * sqrt_t(d2));
+            const T sn = s * (T(0.35355339059327373) * rsqrt_t(d2));  // s / |c|
             if (sn > best) {
               best = sn;
               bid = (ia ? i : j) << 4 | (ia ? j : i);

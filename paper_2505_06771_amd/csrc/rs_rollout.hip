@@ -201,9 +201,10 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
     const float u = unit24(word(pb, i & 3));
     int action = 4;
     float cdf = 0.f;
+    const float inv_tot = 1.0f / tot;
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      cdf += ex[k] / tot;
+      cdf += ex[k] * inv_tot;
       if (action == 4 && k < 4 && u < cdf) action = k;
     }
     if (on) A.actions[((size_t)t * A.E + e) * N + i] = (uint8_t)action;

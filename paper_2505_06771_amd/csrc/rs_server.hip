@@ -318,7 +318,9 @@ rs_status rs_server_create(rs_ctx *ctx, const rs_params *p, int64_t hbm_budget_b
   s->tick_steps = tick_steps;
   // every admitted byte set fits: robots need >= 20 B each, envs >= 49 B
   s->cap_robots = hbm_budget_bytes / kRobotBytes;
-  s->cap_slots = std::min<int64_t>(hbm_budget_bytes / (kEnvBytes + 2 * kRobotBytes), INT32_MAX / 2);
+  // slot table: as many envs as the budget can hold (2 robots each), at most
+  // 2^21; the work-list buffers are sized by it
+  s->cap_slots = std::min<int64_t>(hbm_budget_bytes / (kEnvBytes + 2 * kRobotBytes), 1 << 21);
   s->nrob_of.assign(s->cap_slots, 2);
   s->robots_alloc.init(s->cap_robots);
   s->slots_alloc.init(s->cap_slots);

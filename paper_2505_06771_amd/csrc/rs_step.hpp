@@ -38,12 +38,12 @@ __device__ __forceinline__ void si_to_uni(const SimConst<T> &C, T c, T s, T ux, 
   w = (c * uy - s * ux) * C.inv_l;
   if (C.R > T(0)) {
     const T halfL = T(0.5) * C.L;
-    T phr = (v + halfL * w) / C.R;
-    T phl = (v - halfL * w) / C.R;
+    T phr = (v + halfL * w) * C.inv_R;
+    T phl = (v - halfL * w) * C.inv_R;
     phr = tmin(tmax(phr, -C.wheel_lim), C.wheel_lim);
     phl = tmin(tmax(phl, -C.wheel_lim), C.wheel_lim);
     v = T(0.5) * C.R * (phr + phl);
-    w = C.R * (phr - phl) / C.L;
+    w = C.R_over_L * (phr - phl);
   }
 }
 
@@ -156,7 +156,7 @@ __device__ T max_violation(const SimConst<T> &C, int lane, int i, int N, bool on
       const T d2 = dx * dx + dy * dy, h = d2 - C.rs2;
       const T s = T(2) * (dx * (ia ? uxj - ux : ux - uxj) + dy * (ia ? uyj - uy : uy - uyj)) -
                   C.gamma * (h * h * h);
-      worst = tmax(worst, d2 > T(0) ? s / (T(2.8284271247461903) * sqrt_t(d2)) : s);
+      worst = tmax(worst, d2 > T(0) ? s * (T(0.35355339059327373) * rsqrt_t(d2)) : s);
     }
   }
   return tmax(group_max<G>(worst), T(0));

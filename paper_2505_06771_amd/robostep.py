@@ -63,7 +63,8 @@ class RsPolicy(ctypes.Structure):
 
 
 class RsSchedule(ctypes.Structure):
-    _fields_ = [("block_threads", ctypes.c_int32), ("lanes_per_env", ctypes.c_int32 * 17)]
+    _fields_ = [("block_threads", ctypes.c_int32), ("lanes_per_env", ctypes.c_int32 * 17),
+                ("qp_iters", ctypes.c_int32 * 17)]
 
 
 class RsRequestInfo(ctypes.Structure):

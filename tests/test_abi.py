@@ -64,6 +64,35 @@ def test_params_struct_matches_oracle_constants(R):
         assert getattr(o, f) == getattr(p, f), f
 
 
+def test_struct_layouts_match_the_header(R, tmp_path):
+    """ctypes mirrors of the ABI structs have the C sizes and field offsets."""
+    import subprocess
+
+    src = tmp_path / "sizes.c"
+    fields = {"rs_params": ["seed", "qp_max_iters", "grid"], "rs_batch": ["env_id_base", "episode"],
+              "rs_policy": ["in_dim", "b3"], "rs_schedule": ["qp_iters", "lanes_per_env"],
+              "rs_request_info": ["finish_time", "horizon"],
+              "rs_server_stats": ["running", "peak_bytes"]}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "robostep.h"', "int main(void){"]
+    for st, fs in fields.items():
+        lines.append(f'printf("{st} %zu\\n", sizeof({st}));')
+        for f in fs:
+            lines.append(f'printf("{st}.{f} %zu\\n", offsetof({st}, {f}));')
+    lines.append("return 0;}")
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "sizes"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                  check=True).stdout.splitlines())
+    mirror = {"rs_params": R.RsParams, "rs_batch": R.RsBatch, "rs_policy": R.RsPolicy,
+              "rs_schedule": R.RsSchedule, "rs_request_info": R.RsRequestInfo,
+              "rs_server_stats": R.RsServerStats}
+    for st, cls in mirror.items():
+        assert ctypes.sizeof(cls) == int(out[st]), st
+        for f in fields[st]:
+            assert getattr(cls, f).offset == int(out[f"{st}.{f}"]), f"{st}.{f}"
+
+
 def test_status_strings(R):
     L = R.lib()
     assert L.rs_status_string(0) == b"ok"

@@ -221,8 +221,10 @@ def test_env_step_goto_goal_termination(orc):
     r = rng.uniform(0.04, 0.12, (E, n))
     st["gx"], st["gy"] = st["x"] + r * np.cos(a), st["y"] + r * np.sin(a)
     b = batch_from_states(R, st, n, torch.float32)
-    p = R.params(controller=R.RS_CTRL_GOTO, seed=2)
-    po = orc.Params(controller=1, seed=2)
+    # the controller drives the projection point (l = 0.05 m ahead) onto the
+    # goal, so centres settle l from their goals: use a radius above l
+    p = R.params(controller=R.RS_CTRL_GOTO, goal_radius=0.07, seed=2)
+    po = orc.Params(controller=1, goal_radius=0.07, seed=2)
     banner("env_step goto")
     s = _step_compare(orc, po, R, ctx, p, b, n, steps=60, t0=0,
                       tol={"xy": 1e-5, "th": 6.6e-5, "obs": 1e-5})
