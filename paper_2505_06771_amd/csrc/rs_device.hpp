@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace rs {
 
 constexpr float kPiF = 3.14159265358979323846f;
@@ -115,6 +117,65 @@ template <int G> __device__ __forceinline__ bool group_all(bool pred, int lane) 
 }
 template <int G> __device__ __forceinline__ bool group_any(bool pred, int lane) {
   return group_bits<G>(__ballot(pred), lane) != 0u;
+}
+
+// ---- DPP lane exchange inside a group (VALU-speed, no LDS traffic) --------
+// Controls: quad_perm [1,0,3,2] = 0xB1 (lane ^ 1), quad_perm [2,3,0,1] = 0x4E
+// (lane ^ 2), quad_perm [1,2,3,0] = 0x39, [3,0,1,2] = 0x93, row_ror:n =
+// 0x120 + n (lane l reads lane (l - n) mod 16 of its row), row_mirror = 0x140
+// (l reads 15 - l), row_half_mirror = 0x141 (l reads 7 - l within its half).
+template <int CTRL> __device__ __forceinline__ int dpp_i32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL> __device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(dpp_i32<CTRL>(__float_as_int(v)));
+}
+template <int CTRL> __device__ __forceinline__ int dpp(int v) { return dpp_i32<CTRL>(v); }
+template <int CTRL> __device__ __forceinline__ double dpp(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_i32<CTRL>((int)(b & 0xffffffffll));
+  const int hi = dpp_i32<CTRL>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Value held by lane (i + K) mod G of the caller's group (1 <= K < G).
+template <int G, int K, typename T> __device__ __forceinline__ T grot(T v, int lane) {
+  static_assert(K >= 1 && K < G, "rotation inside the group");
+  if constexpr (G == 2) {
+    return dpp<0xB1>(v);
+  } else if constexpr (G == 4) {
+    return dpp<(K == 1 ? 0x39 : (K == 2 ? 0x4E : 0x93))>(v);
+  } else if constexpr (G == 16) {
+    return dpp<0x120 + (16 - K)>(v);
+  } else {  // G == 8: two rotations of the 16-lane row, pick the one in-group
+    const T a = dpp<0x120 + (16 - K)>(v);  // lane l + K
+    const T b = dpp<0x120 + (8 - K)>(v);   // lane l + K - 8
+    return ((lane & 7) + K < 8) ? a : b;
+  }
+}
+
+// Butterfly over the group with a commutative `op`: every lane of the group
+// ends with the same, bitwise identical, result.
+template <int G, typename T, typename Op> __device__ __forceinline__ T gred(T v, Op op) {
+  v = op(v, dpp<0xB1>(v));
+  if constexpr (G >= 4) v = op(v, dpp<0x4E>(v));
+  if constexpr (G >= 8) v = op(v, dpp<0x141>(v));
+  if constexpr (G >= 16) v = op(v, dpp<0x140>(v));
+  return v;
+}
+template <int G, typename T> __device__ __forceinline__ T gsum(T v) {
+  return gred<G>(v, [](T a, T b) { return a + b; });
+}
+template <int G, typename T> __device__ __forceinline__ T gmax(T v) {
+  return gred<G>(v, [](T a, T b) { return a > b ? a : b; });
+}
+
+// Compile-time loop: f(std::integral_constant<int, K>) for K in [B, E).
+template <int B, int E, typename F> __device__ __forceinline__ void static_for(F &&f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
 }
 
 // Per-launch constants of the simulation, in the state precision T.

@@ -168,11 +168,13 @@ __global__ __launch_bounds__(kBlock) void k_barrier(BarrierArgs<T> A) {
   wall_bounds(A.C, px, py, lox, hix, loy, hiy);
   QPScratch<T, G> *sh = &qs[threadIdx.x / G];
   T ux, uy;
-  const QPInfo info =
-      qp_solve<T, G>(sh, A.C, lane, i, N, on, px, py, unx, uny, lox, hix, loy, hiy, ux, uy);
+  QPActive<T> act;
+  const QPInfo info = qp_solve<T, G>(sh, A.C, lane, i, N, on, px, py, unx, uny, lox, hix, loy,
+                                     hiy, ux, uy, &act);
   if (on) { A.ux[r] = ux; A.uy[r] = uy; }
   if (A.lambda) {
-    // each lane writes the pairs it owns (i, i+k mod N)
+    // each lane writes the pairs it owns (i, i+k mod N); active rows come
+    // from the register slots or, after a restart, from the LDS list
     const int P = N * (N - 1) / 2;
     T *lam = A.lambda + (size_t)e * P;
     for (int k = 1; k <= (N >> 1); ++k) {
@@ -180,8 +182,13 @@ __global__ __launch_bounds__(kBlock) void k_barrier(BarrierArgs<T> A) {
       const int j = i + k >= N ? i + k - N : i + k;
       const int a = i < j ? i : j, b = i < j ? j : i;
       T val = T(0);
-      for (int s = 0; s < info.q; ++s)
-        if (sh->act[s] == (a | (b << 8))) val = T(2) * sh->lam[s];
+      if (info.in_lds) {
+        for (int s = 0; s < info.q; ++s)
+          if (sh->act[s] == (a | (b << 8))) val = T(2) * sh->lam[s];
+      } else {
+        for (int s = 0; s < kQR; ++s)
+          if (s < info.q && act.sa[s] == a && act.sb[s] == b) val = T(2) * act.slam[s];
+      }
       lam[pair_index(a, b, N)] = val;
     }
   }

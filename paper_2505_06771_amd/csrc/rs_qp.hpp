@@ -107,20 +107,22 @@ __device__ __forceinline__ T gram_entry(int as, int bs, T dxs, T dys, int at, in
 struct QPInfo {
   int status;  // 0 solved, 1 infeasible, 2 iteration cap / numerical failure
   int iters;   // active-set iterations
-  int q;       // active pairwise rows at exit (in sh->act / sh->lam)
+  int q;       // active pairwise rows at exit
+  int in_lds;  // 1: the rows are in sh->act / sh->lam (general solver)
 };
 
-// Solve the certificate for the group's environment. Every lane of the group
-// must call this together (uniform control flow within the group). `i` is the
-// robot index (lane in group), `on` = i < N. On return (ux, uy) is the
-// command; for status 1 it is the per-coordinate fallback.
+// General solver with the active set in LDS (any number of active rows).
+// Every lane of the group must call this together (uniform control flow
+// within the group). `i` is the robot index (lane in group), `on` = i < N. On
+// return (ux, uy) is the command; for status 1 it is the per-coordinate
+// fallback. Used when the register-resident solver below runs out of slots.
 template <typename T, int G>
-__device__ QPInfo qp_solve(QPScratch<T, G> *sh, const SimConst<T> &C, int lane, int i, int N,
+__device__ __attribute__((noinline)) QPInfo qp_solve_lds(QPScratch<T, G> *sh, const SimConst<T> &C, int lane, int i, int N,
                            bool on, T px, T py, T uhx, T uhy, T lox, T hix, T loy, T hiy, T &ux,
                            T &uy) {
   const int base = lane & ~(G - 1);
   const T BIG = big_v<T>();
-  QPInfo info{0, 0, 0};
+  QPInfo info{0, 0, 0, 1};
 
   // --- empty box: infeasible, closed-form fallback -------------------------
   const bool crossed = on && (lox > hix || loy > hiy);
@@ -378,6 +380,371 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, const SimConst<T> &C, int lane, 
     }
   }
   info.q = dead ? 0 : q;
+  return info;
+}
+
+}  // namespace rs
+
+namespace rs {
+
+// ---------------------------------------------------------------------------
+// Register-resident solver (the hot path). Same method as qp_solve_lds, but
+//  * the active pairwise rows live in kQR group-uniform register slots, so
+//    the q x q Gram/Cholesky algebra is straight-line code on registers;
+//  * a lane owns the pairs (i, (i+K) mod G), K = 1..G/2 (K = G/2 only for
+//    i < G/2), whose geometry (D, b, 1/|c|) is computed once per solve from
+//    DPP rotations of the projection points;
+//  * every cross-lane quantity (argmax with the row's data as payload, |z|^2,
+//    the violation of the entering row, the blocking step) is a DPP butterfly
+//    over the group: no LDS traffic at all.
+// When a row must enter while all slots are taken, or the Gram system loses
+// positive definiteness, the general solver restarts from scratch.
+// ---------------------------------------------------------------------------
+constexpr int kQR = 4;
+
+template <typename T> struct QPActive {
+  int q;
+  int sa[kQR], sb[kQR];
+  T slam[kQR];
+};
+
+template <int G, typename T>
+__device__ __forceinline__ void gargmax_payload(T &v, int &id, T &p0, T &p1, T &p2) {
+  auto step = [&](auto cc) {
+    constexpr int CT = decltype(cc)::value;
+    const T w = dpp<CT>(v), q0 = dpp<CT>(p0), q1 = dpp<CT>(p1), q2 = dpp<CT>(p2);
+    const int j = dpp<CT>(id);
+    if (w > v || (w == v && j < id)) { v = w; id = j; p0 = q0; p1 = q1; p2 = q2; }
+  };
+  step(std::integral_constant<int, 0xB1>{});
+  if constexpr (G >= 4) step(std::integral_constant<int, 0x4E>{});
+  if constexpr (G >= 8) step(std::integral_constant<int, 0x141>{});
+  if constexpr (G >= 16) step(std::integral_constant<int, 0x140>{});
+}
+
+template <int G, typename T> __device__ __forceinline__ void gargmin(T &v, int &id) {
+  auto step = [&](auto cc) {
+    constexpr int CT = decltype(cc)::value;
+    const T w = dpp<CT>(v);
+    const int j = dpp<CT>(id);
+    if (w < v || (w == v && j < id)) { v = w; id = j; }
+  };
+  step(std::integral_constant<int, 0xB1>{});
+  if constexpr (G >= 4) step(std::integral_constant<int, 0x4E>{});
+  if constexpr (G >= 8) step(std::integral_constant<int, 0x141>{});
+  if constexpr (G >= 16) step(std::integral_constant<int, 0x140>{});
+}
+
+// Owner lane and rotation of pair (a, b), a < b, under the mod-G ownership.
+template <int G> __device__ __forceinline__ void pair_owner_g(int a, int b, int &owner, int &k) {
+  const int d = b - a;
+  if (2 * d <= G) { owner = a; k = d; }
+  else { owner = b; k = G - d; }
+}
+
+template <typename T, int G>
+__device__ QPInfo qp_solve(QPScratch<T, G> *sh, const SimConst<T> &C, int lane, int i, int N,
+                           bool on, T px, T py, T uhx, T uhy, T lox, T hix, T loy, T hiy, T &ux,
+                           T &uy, QPActive<T> *act_out = nullptr) {
+  constexpr int KH = G / 2;
+  const T BIG = big_v<T>();
+  QPInfo info{0, 0, 0, 0};
+
+  // --- geometry of the owned pairs ------------------------------------------
+  T cdx[KH], cdy[KH], cb[KH], crn[KH];
+  int cpid[KH];
+  bool coincide = false;
+  static_for<1, KH + 1>([&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    const T pxj = grot<G, K>(px, lane), pyj = grot<G, K>(py, lane);
+    const int j = (i + K) & (G - 1);
+    const bool valid = on && j < N && !(2 * K == G && i >= KH);
+    const bool ia = i < j;
+    const T dx = ia ? px - pxj : pxj - px;
+    const T dy = ia ? py - pyj : pyj - py;
+    const T d2 = dx * dx + dy * dy;
+    const T h = d2 - C.rs2;
+    const T bb = C.gamma * (h * h * h);
+    const bool cand = valid && (T(4) * C.vmax * (tabs(dx) + tabs(dy)) > bb);
+    cdx[K - 1] = dx;
+    cdy[K - 1] = dy;
+    cb[K - 1] = bb;
+    crn[K - 1] = d2 > T(0) ? T(0.35355339059327373) * rsqrt_t(d2) : T(0);
+    cpid[K - 1] = (cand && d2 > T(0)) ? ((ia ? i : j) << 4 | (ia ? j : i)) : -1;
+    if (cand && !(d2 > T(0)) && bb < T(0)) coincide = true;
+  });
+  bool dead = group_any<G>(coincide || (on && (lox > hix || loy > hiy)), lane);
+
+  // --- start: clip to the box; active bounds fix their coordinate ----------
+  int fx = 0, fy = 0;
+  T mux = T(0), muy = T(0);
+  ux = uhx;
+  uy = uhy;
+  if (on) {
+    if (uhx > hix) { ux = hix; fx = 1; mux = uhx - hix; }
+    else if (uhx < lox) { ux = lox; fx = -1; mux = lox - uhx; }
+    if (uhy > hiy) { uy = hiy; fy = 1; muy = uhy - hiy; }
+    else if (uhy < loy) { uy = loy; fy = -1; muy = loy - uhy; }
+  }
+
+  int q = 0;
+  int sa[kQR], sb[kQR];
+  T sdx[kQR], sdy[kQR], slam[kQR];
+#pragma unroll
+  for (int a = 0; a < kQR; ++a) { sa[a] = sb[a] = -1; sdx[a] = sdy[a] = slam[a] = T(0); }
+  uint32_t own_act = 0;
+  const int cap = C.qp_cap > 0 ? C.qp_cap : 8 * N + 32;
+  bool restart = false;
+
+  while (!dead) {
+    // --- most violated constraint (argmax carries the row's data) ----------
+    T best = C.tol_add, bdx = T(0), bdy = T(0), bbb = T(0);
+    int bid = -1;
+    if (on) {
+      if (fx == 0) {
+        const T su = ux - hix, sl = lox - ux;
+        if (su > best) { best = su; bid = 256 + 4 * i; }
+        else if (sl > best) { best = sl; bid = 256 + 4 * i + 1; }
+      }
+      if (fy == 0) {
+        const T su = uy - hiy, sl = loy - uy;
+        if (su > best) { best = su; bid = 256 + 4 * i + 2; }
+        else if (sl > best) { best = sl; bid = 256 + 4 * i + 3; }
+      }
+    }
+    static_for<1, KH + 1>([&](auto kc) {
+      constexpr int K = decltype(kc)::value;
+      const T uxj = grot<G, K>(ux, lane), uyj = grot<G, K>(uy, lane);
+      if (cpid[K - 1] >= 0 && !((own_act >> K) & 1u)) {
+        const bool ia = i < ((i + K) & (G - 1));
+        const T dux = ia ? uxj - ux : ux - uxj;
+        const T duy = ia ? uyj - uy : uy - uyj;
+        const T sn = (T(2) * (cdx[K - 1] * dux + cdy[K - 1] * duy) - cb[K - 1]) * crn[K - 1];
+        if (sn > best) {
+          best = sn;
+          bid = cpid[K - 1];
+          bdx = cdx[K - 1];
+          bdy = cdy[K - 1];
+          bbb = cb[K - 1];
+        }
+      }
+    });
+    gargmax_payload<G>(best, bid, bdx, bdy, bbb);
+    if (bid < 0) break;  // optimal
+    if (++info.iters > cap) { info.status = 2; break; }
+
+    const bool p_pair = bid < 256;
+    const int pa = p_pair ? (bid >> 4) : ((bid - 256) >> 2);
+    const int pb = p_pair ? (bid & 15) : -1;
+    const int pk = p_pair ? 0 : (((bid - 256) >> 1) & 1);
+    const int psig = p_pair ? 0 : (((bid - 256) & 1) ? -1 : 1);
+    const T dpx = bdx, dpy = bdy, bp = bbb;
+    T lam_p = T(0);
+    bool added = false;
+    for (int inner = 0; inner < cap && !added; ++inner) {
+      const uint32_t freex = ~group_bits<G>(__ballot(fx != 0), lane);
+      const uint32_t freey = ~group_bits<G>(__ballot(fy != 0), lane);
+      // Gram system of the active rows over the free coordinates (registers)
+      T L[kQR * (kQR + 1) / 2], Linv[kQR], rv[kQR], w[kQR];
+      bool pd = true;
+#pragma unroll
+      for (int a = 0; a < kQR; ++a) {
+        Linv[a] = T(0);
+        rv[a] = T(0);
+        w[a] = T(0);
+#pragma unroll
+        for (int b = 0; b <= a; ++b) L[tri(a, b)] = T(0);
+      }
+#pragma unroll
+      for (int a = 0; a < kQR; ++a) {
+        if (a < q) {
+#pragma unroll
+          for (int b = 0; b <= a; ++b) {
+            T sgm = gram_entry<T>(sa[a], sb[a], sdx[a], sdy[a], sa[b], sb[b], sdx[b], sdy[b], freex,
+                                  freey);
+#pragma unroll
+            for (int k2 = 0; k2 < b; ++k2) sgm -= L[tri(a, k2)] * L[tri(b, k2)];
+            if (b == a) {
+              pd = pd && (sgm > T(0));
+              const T rs = sgm > T(0) ? rsqrt_t(sgm) : T(0);
+              L[tri(a, a)] = sgm * rs;
+              Linv[a] = rs;
+            } else {
+              L[tri(a, b)] = sgm * Linv[b];
+            }
+          }
+        }
+      }
+      if (!pd) { restart = true; break; }
+      // g = C_S^free c_p, forward and backward substitution
+#pragma unroll
+      for (int a = 0; a < kQR; ++a) {
+        if (a < q) {
+          T g;
+          if (p_pair) {
+            g = gram_entry<T>(sa[a], sb[a], sdx[a], sdy[a], pa, pb, dpx, dpy, freex, freey);
+          } else {
+            const T comp = pk ? sdy[a] : sdx[a];
+            g = (pa == sa[a]) ? T(-2) * comp : ((pa == sb[a]) ? T(2) * comp : T(0));
+            g *= T(psig);
+          }
+#pragma unroll
+          for (int k2 = 0; k2 < a; ++k2) g -= L[tri(a, k2)] * w[k2];
+          w[a] = g * Linv[a];
+        }
+      }
+#pragma unroll
+      for (int a = kQR - 1; a >= 0; --a) {
+        if (a < q) {
+          T sgm = w[a];
+#pragma unroll
+          for (int k2 = a + 1; k2 < kQR; ++k2)
+            if (k2 < q) sgm -= L[tri(k2, a)] * rv[k2];
+          rv[a] = sgm * Linv[a];
+        }
+      }
+      // (C_S^T r) and c_p at my robot
+      T crx = T(0), cry = T(0);
+#pragma unroll
+      for (int a = 0; a < kQR; ++a) {
+        if (a < q) {
+          if (i == sa[a]) { crx -= T(2) * sdx[a] * rv[a]; cry -= T(2) * sdy[a] * rv[a]; }
+          else if (i == sb[a]) { crx += T(2) * sdx[a] * rv[a]; cry += T(2) * sdy[a] * rv[a]; }
+        }
+      }
+      T cpx = T(0), cpy = T(0);
+      if (p_pair) {
+        if (i == pa) { cpx = T(-2) * dpx; cpy = T(-2) * dpy; }
+        else if (i == pb) { cpx = T(2) * dpx; cpy = T(2) * dpy; }
+      } else if (i == pa) {
+        if (pk) cpy = T(psig); else cpx = T(psig);
+      }
+      if (!on) { crx = cry = cpx = cpy = T(0); }
+      const T zx = fx == 0 ? cpx - crx : T(0);
+      const T zy = fy == 0 ? cpy - cry : T(0);
+      const T rfx = fx != 0 ? T(fx) * (cpx - crx) : T(0);
+      const T rfy = fy != 0 ? T(fy) * (cpy - cry) : T(0);
+      const T zz = gsum<G>(zx * zx + zy * zy);
+      T cpn2 = T(1);
+      if (p_pair) {
+        T sa2 = T(0), sb2 = T(0);
+        if ((freex >> pa) & 1u) sa2 += dpx * dpx;
+        if ((freey >> pa) & 1u) sa2 += dpy * dpy;
+        if ((freex >> pb) & 1u) sb2 += dpx * dpx;
+        if ((freey >> pb) & 1u) sb2 += dpy * dpy;
+        cpn2 = T(4) * (sa2 + sb2);
+      }
+      // blocking step t1 over active rows (uniform) and my fixed bounds
+      T t1 = BIG;
+      int drop = -1;
+#pragma unroll
+      for (int a = 0; a < kQR; ++a) {
+        if (a < q && rv[a] > C.eps_r) {
+          const T ratio = slam[a] / rv[a];
+          if (ratio < t1) { t1 = ratio; drop = a; }
+        }
+      }
+      if (on && fx != 0 && rfx > C.eps_r) {
+        const T ratio = mux / rfx;
+        if (ratio < t1 || (ratio == t1 && drop < 0)) { t1 = ratio; drop = 1024 + 2 * i; }
+      }
+      if (on && fy != 0 && rfy > C.eps_r) {
+        const T ratio = muy / rfy;
+        if (ratio < t1 || (ratio == t1 && drop < 0)) { t1 = ratio; drop = 1024 + 2 * i + 1; }
+      }
+      gargmin<G>(t1, drop);
+      // current violation of p
+      T contrib = T(0);
+      if (on) {
+        if (p_pair) {
+          if (i == pa) contrib = T(-2) * (dpx * ux + dpy * uy);
+          else if (i == pb) contrib = T(2) * (dpx * ux + dpy * uy);
+        } else if (i == pa) {
+          contrib = pk ? (psig > 0 ? uy - hiy : loy - uy) : (psig > 0 ? ux - hix : lox - ux);
+        }
+      }
+      const T sp = gsum<G>(contrib) - (p_pair ? bp : T(0));
+      const bool z_ok = zz > C.eps_z * cpn2;
+      const T t2 = z_ok ? sp / zz : BIG;
+      if (drop < 0 && !z_ok) { dead = true; break; }
+      const bool full = z_ok && (drop < 0 || t2 <= t1);
+      const T t = full ? t2 : t1;
+      if (full && p_pair && q == kQR) { restart = true; break; }  // no slot left
+      if (z_ok) {
+        ux -= t * zx;
+        uy -= t * zy;
+      }
+#pragma unroll
+      for (int a = 0; a < kQR; ++a)
+        if (a < q) slam[a] -= t * rv[a];
+      if (on) {
+        mux -= t * rfx;
+        muy -= t * rfy;
+      }
+      lam_p += t;
+      if (full) {
+        if (p_pair) {
+#pragma unroll
+          for (int a = 0; a < kQR; ++a) {
+            if (a == q) { sa[a] = pa; sb[a] = pb; sdx[a] = dpx; sdy[a] = dpy; slam[a] = lam_p; }
+          }
+          ++q;
+          int owner, kk;
+          pair_owner_g<G>(pa, pb, owner, kk);
+          if (i == owner) own_act |= 1u << kk;
+        } else if (i == pa) {
+          if (pk) { fy = psig; muy = lam_p; uy = psig > 0 ? hiy : loy; }
+          else { fx = psig; mux = lam_p; ux = psig > 0 ? hix : lox; }
+        }
+        added = true;
+      } else if (drop >= 1024) {
+        const int r = (drop - 1024) >> 1, cc = (drop - 1024) & 1;
+        if (i == r) {
+          if (cc) { fy = 0; muy = T(0); } else { fx = 0; mux = T(0); }
+        }
+      } else {
+        int owner = 0, kk = 0;
+#pragma unroll
+        for (int a = 0; a < kQR; ++a)
+          if (a == drop) pair_owner_g<G>(sa[a], sb[a], owner, kk);
+        if (i == owner) own_act &= ~(1u << kk);
+#pragma unroll
+        for (int a = 0; a < kQR - 1; ++a) {
+          if (a >= drop && a + 1 < q) {
+            sa[a] = sa[a + 1]; sb[a] = sb[a + 1];
+            sdx[a] = sdx[a + 1]; sdy[a] = sdy[a + 1]; slam[a] = slam[a + 1];
+          }
+        }
+        --q;
+      }
+      if (++info.iters > cap) { info.status = 2; break; }
+    }
+    if (restart || info.status == 2 || dead) break;
+  }
+
+  if (restart && !dead) {
+    // more active rows than register slots (or a degenerate Gram system):
+    // solve again with the general solver
+    return qp_solve_lds<T, G>(sh, C, lane, i, N, on, px, py, uhx, uhy, lox, hix, loy, hiy, ux, uy);
+  }
+  if (dead) {
+    info.status = 1;
+    q = 0;
+    if (on) {
+      ux = lox <= hix ? tmin(tmax(uhx, lox), hix) : T(0.5) * (lox + hix);
+      uy = loy <= hiy ? tmin(tmax(uhy, loy), hiy) : T(0.5) * (loy + hiy);
+    }
+  }
+  info.q = q;
+  if (act_out) {
+    act_out->q = q;
+#pragma unroll
+    for (int a = 0; a < kQR; ++a) {
+      act_out->sa[a] = sa[a];
+      act_out->sb[a] = sb[a];
+      act_out->slam[a] = slam[a];
+    }
+  }
   return info;
 }
 

@@ -113,25 +113,27 @@ __device__ void reset_env(const SimConst<T> &C, uint32_t env_id, uint32_t episod
 }
 
 // Observation of robot i: x, y, cos th, sin th, (x_j - x_i, y_j - y_i) for
-// j != i ascending, g_i - (x_i, y_i). Written to o[0 .. 2N+3].
+// j != i ascending, g_i - (x_i, y_i). Written to o[0 .. 2N+3]. Neighbour
+// positions arrive by DPP rotations inside the group.
 template <typename T, int G>
 __device__ __forceinline__ void write_obs(T *o, int lane, int i, int N, bool on, T x, T y, T c,
                                           T s, T gx, T gy) {
-  const int base = lane & ~(G - 1);
   if (on) {
     o[0] = x;
     o[1] = y;
     o[2] = c;
     o[3] = s;
   }
-  for (int j = 0; j < N; ++j) {
-    const T xj = __shfl(x, base + j, 64), yj = __shfl(y, base + j, 64);
-    if (on && j != i) {
+  static_for<1, G>([&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    const T xj = grot<G, K>(x, lane), yj = grot<G, K>(y, lane);
+    const int j = (i + K) & (G - 1);
+    if (on && j < N) {
       const int m = 4 + 2 * (j < i ? j : j - 1);
       o[m] = xj - x;
       o[m + 1] = yj - y;
     }
-  }
+  });
   if (on) {
     o[2 * N + 2] = gx - x;
     o[2 * N + 3] = gy - y;
@@ -210,7 +212,7 @@ __device__ StepOut<T> env_step_group(const SimConst<T> &C, QPScratch<T, G> *sh, 
     const T ex = x - gx, ey = y - gy;
     dist = sqrt_t(ex * ex + ey * ey);
   }
-  out.reward = -group_sum<G>(dist);
+  out.reward = -gsum<G>(dist);
   const bool near_all = group_all<G>(!on || dist < C.goal_r, lane);
   out.done = (C.goal_r > T(0) && near_all) || (C.max_steps > 0 && step >= C.max_steps);
   if (out.done) {
