@@ -22,7 +22,9 @@ template <typename T> __device__ __forceinline__ T pi_v();
 template <> __device__ __forceinline__ float pi_v<float>() { return kPiF; }
 template <> __device__ __forceinline__ double pi_v<double>() { return kPiD; }
 
-__device__ __forceinline__ void sincos_t(float a, float *s, float *c) { sincosf(a, s, c); }
+// FP32 uses the hardware sine/cosine: headings stay in [-pi, pi], where its
+// error (~1e-6) is far inside the tolerances of positions and observations.
+__device__ __forceinline__ void sincos_t(float a, float *s, float *c) { __sincosf(a, s, c); }
 __device__ __forceinline__ void sincos_t(double a, double *s, double *c) { sincos(a, s, c); }
 __device__ __forceinline__ float sqrt_t(float a) { return sqrtf(a); }
 __device__ __forceinline__ double sqrt_t(double a) { return sqrt(a); }

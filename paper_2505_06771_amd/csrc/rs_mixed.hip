@@ -51,7 +51,7 @@ __device__ void run_tile(const RunArgs &A, char *wave_lds, int lane, int first, 
   if (A.steps_per_env) nsteps = min(nsteps, A.steps_per_env[e]);
   const int64_t tb = A.t_start ? A.t_start[e] : (int64_t)A.t0;
   float s, c;
-  sincosf(th, &s, &c);
+  sincos_t(th, &s, &c);
   float rsum = 0.f;
   for (int k = 0; k < nsteps; ++k) {
     const int action = drawn_action(C.key0, C.key1, env_id, (uint32_t)(tb + k), i);

@@ -117,7 +117,7 @@ struct QPInfo {
 // return (ux, uy) is the command; for status 1 it is the per-coordinate
 // fallback. Used when the register-resident solver below runs out of slots.
 template <typename T, int G>
-__device__ __attribute__((noinline)) QPInfo qp_solve_lds(QPScratch<T, G> *sh, const SimConst<T> &C, int lane, int i, int N,
+__device__ __attribute__((noinline)) QPInfo qp_solve_lds(QPScratch<T, G> *sh, const SimConst<T> C, int lane, int i, int N,
                            bool on, T px, T py, T uhx, T uhy, T lox, T hix, T loy, T hiy, T &ux,
                            T &uy) {
   const int base = lane & ~(G - 1);
@@ -490,8 +490,19 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, const SimConst<T> &C, int lane, 
   int q = 0;
   int sa[kQR], sb[kQR];
   T sdx[kQR], sdy[kQR], slam[kQR];
+  // Cholesky factor of the Gram system of the active rows, kept across
+  // iterations: a row entering by a full step appends [w, |z|] (since
+  // |z|^2 = c_p^T c_p - |L^-1 g|^2); any other change refactors.
+  T L[kQR * (kQR + 1) / 2], Linv[kQR];
+  bool lvalid = true;
 #pragma unroll
-  for (int a = 0; a < kQR; ++a) { sa[a] = sb[a] = -1; sdx[a] = sdy[a] = slam[a] = T(0); }
+  for (int a = 0; a < kQR; ++a) {
+    sa[a] = sb[a] = -1;
+    sdx[a] = sdy[a] = slam[a] = T(0);
+    Linv[a] = T(0);
+#pragma unroll
+    for (int b = 0; b <= a; ++b) L[tri(a, b)] = T(0);
+  }
   uint32_t own_act = 0;
   const int cap = C.qp_cap > 0 ? C.qp_cap : 8 * N + 32;
   bool restart = false;
@@ -544,63 +555,62 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, const SimConst<T> &C, int lane, 
     for (int inner = 0; inner < cap && !added; ++inner) {
       const uint32_t freex = ~group_bits<G>(__ballot(fx != 0), lane);
       const uint32_t freey = ~group_bits<G>(__ballot(fy != 0), lane);
-      // Gram system of the active rows over the free coordinates (registers)
-      T L[kQR * (kQR + 1) / 2], Linv[kQR], rv[kQR], w[kQR];
-      bool pd = true;
+      T rv[kQR], w[kQR];
 #pragma unroll
-      for (int a = 0; a < kQR; ++a) {
-        Linv[a] = T(0);
-        rv[a] = T(0);
-        w[a] = T(0);
+      for (int a = 0; a < kQR; ++a) { rv[a] = T(0); w[a] = T(0); }
+      if (q > 0) {
+        if (!lvalid) {
+          // refactor the Gram system over the current free coordinates
+          bool pd = true;
 #pragma unroll
-        for (int b = 0; b <= a; ++b) L[tri(a, b)] = T(0);
-      }
+          for (int a = 0; a < kQR; ++a) {
+            if (a < q) {
 #pragma unroll
-      for (int a = 0; a < kQR; ++a) {
-        if (a < q) {
+              for (int b = 0; b <= a; ++b) {
+                T sgm = gram_entry<T>(sa[a], sb[a], sdx[a], sdy[a], sa[b], sb[b], sdx[b], sdy[b],
+                                      freex, freey);
 #pragma unroll
-          for (int b = 0; b <= a; ++b) {
-            T sgm = gram_entry<T>(sa[a], sb[a], sdx[a], sdy[a], sa[b], sb[b], sdx[b], sdy[b], freex,
-                                  freey);
-#pragma unroll
-            for (int k2 = 0; k2 < b; ++k2) sgm -= L[tri(a, k2)] * L[tri(b, k2)];
-            if (b == a) {
-              pd = pd && (sgm > T(0));
-              const T rs = sgm > T(0) ? rsqrt_t(sgm) : T(0);
-              L[tri(a, a)] = sgm * rs;
-              Linv[a] = rs;
-            } else {
-              L[tri(a, b)] = sgm * Linv[b];
+                for (int k2 = 0; k2 < b; ++k2) sgm -= L[tri(a, k2)] * L[tri(b, k2)];
+                if (b == a) {
+                  pd = pd && (sgm > T(0));
+                  const T rs = sgm > T(0) ? rsqrt_t(sgm) : T(0);
+                  L[tri(a, a)] = sgm * rs;
+                  Linv[a] = rs;
+                } else {
+                  L[tri(a, b)] = sgm * Linv[b];
+                }
+              }
             }
           }
+          if (!pd) { restart = true; break; }
+          lvalid = true;
         }
-      }
-      if (!pd) { restart = true; break; }
-      // g = C_S^free c_p, forward and backward substitution
+        // g = C_S^free c_p, then w = L^-1 g and r = L^-T w
 #pragma unroll
-      for (int a = 0; a < kQR; ++a) {
-        if (a < q) {
-          T g;
-          if (p_pair) {
-            g = gram_entry<T>(sa[a], sb[a], sdx[a], sdy[a], pa, pb, dpx, dpy, freex, freey);
-          } else {
-            const T comp = pk ? sdy[a] : sdx[a];
-            g = (pa == sa[a]) ? T(-2) * comp : ((pa == sb[a]) ? T(2) * comp : T(0));
-            g *= T(psig);
+        for (int a = 0; a < kQR; ++a) {
+          if (a < q) {
+            T g;
+            if (p_pair) {
+              g = gram_entry<T>(sa[a], sb[a], sdx[a], sdy[a], pa, pb, dpx, dpy, freex, freey);
+            } else {
+              const T comp = pk ? sdy[a] : sdx[a];
+              g = (pa == sa[a]) ? T(-2) * comp : ((pa == sb[a]) ? T(2) * comp : T(0));
+              g *= T(psig);
+            }
+#pragma unroll
+            for (int k2 = 0; k2 < a; ++k2) g -= L[tri(a, k2)] * w[k2];
+            w[a] = g * Linv[a];
           }
-#pragma unroll
-          for (int k2 = 0; k2 < a; ++k2) g -= L[tri(a, k2)] * w[k2];
-          w[a] = g * Linv[a];
         }
-      }
 #pragma unroll
-      for (int a = kQR - 1; a >= 0; --a) {
-        if (a < q) {
-          T sgm = w[a];
+        for (int a = kQR - 1; a >= 0; --a) {
+          if (a < q) {
+            T sgm = w[a];
 #pragma unroll
-          for (int k2 = a + 1; k2 < kQR; ++k2)
-            if (k2 < q) sgm -= L[tri(k2, a)] * rv[k2];
-          rv[a] = sgm * Linv[a];
+            for (int k2 = a + 1; k2 < kQR; ++k2)
+              if (k2 < q) sgm -= L[tri(k2, a)] * rv[k2];
+            rv[a] = sgm * Linv[a];
+          }
         }
       }
       // (C_S^T r) and c_p at my robot
@@ -684,17 +694,28 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, const SimConst<T> &C, int lane, 
       lam_p += t;
       if (full) {
         if (p_pair) {
+          // append the row and extend the factor: L[q] = [w, |z|]
+          const T rz = rsqrt_t(zz);
 #pragma unroll
           for (int a = 0; a < kQR; ++a) {
-            if (a == q) { sa[a] = pa; sb[a] = pb; sdx[a] = dpx; sdy[a] = dpy; slam[a] = lam_p; }
+            if (a == q) {
+              sa[a] = pa; sb[a] = pb; sdx[a] = dpx; sdy[a] = dpy; slam[a] = lam_p;
+#pragma unroll
+              for (int k2 = 0; k2 < a; ++k2) L[tri(a, k2)] = w[k2];
+              L[tri(a, a)] = zz * rz;
+              Linv[a] = rz;
+            }
           }
           ++q;
           int owner, kk;
           pair_owner_g<G>(pa, pb, owner, kk);
           if (i == owner) own_act |= 1u << kk;
-        } else if (i == pa) {
-          if (pk) { fy = psig; muy = lam_p; uy = psig > 0 ? hiy : loy; }
-          else { fx = psig; mux = lam_p; ux = psig > 0 ? hix : lox; }
+        } else {
+          if (i == pa) {
+            if (pk) { fy = psig; muy = lam_p; uy = psig > 0 ? hiy : loy; }
+            else { fx = psig; mux = lam_p; ux = psig > 0 ? hix : lox; }
+          }
+          lvalid = false;  // the free coordinates changed
         }
         added = true;
       } else if (drop >= 1024) {
@@ -702,6 +723,7 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, const SimConst<T> &C, int lane, 
         if (i == r) {
           if (cc) { fy = 0; muy = T(0); } else { fx = 0; mux = T(0); }
         }
+        lvalid = false;
       } else {
         int owner = 0, kk = 0;
 #pragma unroll
@@ -716,6 +738,7 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, const SimConst<T> &C, int lane, 
           }
         }
         --q;
+        lvalid = false;
       }
       if (++info.iters > cap) { info.status = 2; break; }
     }

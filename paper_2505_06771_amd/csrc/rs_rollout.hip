@@ -63,9 +63,18 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
   __shared__ QPScratch<float, G> qs[kRollBlock / G];
   __shared__ __attribute__((aligned(16))) float obs_lds[kRollWaves][64 * 32];
   __shared__ float4 logit_lds[kRollWaves][64 * 2];
+  // hidden-layer biases in the accumulator layout: [layer][tile][lane group]
+  __shared__ float4 bias_lds[2][4][4];
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
+  if (threadIdx.x < 32) {
+    const int layer = threadIdx.x >> 4, mt = (threadIdx.x >> 2) & 3, gg = threadIdx.x & 3;
+    const float *bsrc = layer ? A.b2 : A.b1;
+    bias_lds[layer][mt][gg] = make_float4(bsrc[16 * mt + 4 * gg], bsrc[16 * mt + 4 * gg + 1],
+                                          bsrc[16 * mt + 4 * gg + 2], bsrc[16 * mt + 4 * gg + 3]);
+  }
+  __syncthreads();  // the only block-wide barrier, before any wavefront leaves
   const int i = lane & (G - 1);
   const int grp = lane / G;
   const int e0 = (blockIdx.x * kRollWaves + wave) * EPW;
@@ -82,12 +91,12 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
   if (on) { x = A.x[r]; y = A.y[r]; th = A.th[r]; gx = A.gx[r]; gy = A.gy[r]; }
   if (env_ok) { step = A.step[e]; episode = A.episode[e]; }
   float s, c;
-  sincosf(th, &s, &c);
+  sincos_t(th, &s, &c);
 
   // ---- policy weights into registers (MFMA A-operand fragments) ----------
   const int g = lane >> 4, c16 = lane & 15;
   bf16x8 w1f[4], w2f[4][2], w3f[2];
-  floatx4 b1f[4], b2f[4], b3f;
+  floatx4 b3f;
   const __bf16 zero = (__bf16)0.0f;
 #pragma unroll
   for (int mt = 0; mt < 4; ++mt) {
@@ -95,11 +104,6 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
     for (int j = 0; j < 8; ++j) {
       const int f = 8 * g + j;
       w1f[mt][j] = f < D ? A.w1[f * 64 + 16 * mt + c16] : zero;
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      b1f[mt][j] = A.b1[16 * mt + 4 * g + j];
-      b2f[mt][j] = A.b2[16 * mt + 4 * g + j];
     }
 #pragma unroll
     for (int sk = 0; sk < 2; ++sk)
@@ -121,6 +125,7 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
   const bool vec4 = ((N * D) & 3) == 0;
   const int row = grp * N + i;              // packed LDS row of my robot
 
+  uint4 qblk = make_uint4(0u, 0u, 0u, 0u);  // this lane's Philox block (G >= 4)
   for (int t = 0; t < A.H; ++t) {
     // ---- 1. observation -> LDS (packed) -> HBM --------------------------
     float *o = obs_w + row * D;
@@ -161,8 +166,11 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
       }
       floatx4 h1[4];
 #pragma unroll
-      for (int mt = 0; mt < 4; ++mt)
-        h1[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1f[mt], xb, b1f[mt], 0, 0, 0);
+      for (int mt = 0; mt < 4; ++mt) {
+        const float4 bb = bias_lds[0][mt][g];
+        const floatx4 b1v = {bb.x, bb.y, bb.z, bb.w};
+        h1[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1f[mt], xb, b1v, 0, 0, 0);
+      }
       bf16x8 hb[2];
 #pragma unroll
       for (int sk = 0; sk < 2; ++sk)
@@ -171,7 +179,9 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
       floatx4 h2[4];
 #pragma unroll
       for (int mo = 0; mo < 4; ++mo) {
-        h2[mo] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2f[mo][0], hb[0], b2f[mo], 0, 0, 0);
+        const float4 bb = bias_lds[1][mo][g];
+        const floatx4 b2v = {bb.x, bb.y, bb.z, bb.w};
+        h2[mo] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2f[mo][0], hb[0], b2v, 0, 0, 0);
         h2[mo] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2f[mo][1], hb[1], h2[mo], 0, 0, 0);
       }
       bf16x8 hc[2];
@@ -194,11 +204,32 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
     for (int k = 1; k < 5; ++k) mx = fmaxf(mx, l5[k]);
     float ex[5], tot = 0.f;
 #pragma unroll
-    for (int k = 0; k < 5; ++k) { ex[k] = expf(l5[k] - mx); tot += ex[k]; }
+    for (int k = 0; k < 5; ++k) { ex[k] = __expf(l5[k] - mx); tot += ex[k]; }
     const uint32_t env_id = A.env_base + (uint32_t)e;
-    const uint4 pb = stream_block(A.C.key0, A.C.key1, env_id, A.t0 + (uint32_t)t, kPolicy,
-                                  (uint32_t)(i >> 2), 0u);
-    const float u = unit24(word(pb, i & 3));
+    // Sampling word of robot i at stream time t0 + t: word i&3 of block
+    // (env_id, t0 + t, 1<<24 | i>>2, 0). With G >= 4 a lane quad holds the 4
+    // robots of one block, so every 4 steps quad lane j computes the block of
+    // step t + j and the others read it by DPP.
+    uint32_t rbits;
+    if constexpr (G >= 4) {
+      const int ph = t & 3;
+      if (ph == 0) {
+        qblk = stream_block(A.C.key0, A.C.key1, env_id, A.t0 + (uint32_t)(t + (i & 3)), kPolicy,
+                            (uint32_t)(i >> 2), 0u);
+      }
+      uint4 src;
+      switch (ph) {
+        case 0: src = make_uint4(dpp<0x00>((int)qblk.x), dpp<0x00>((int)qblk.y), dpp<0x00>((int)qblk.z), dpp<0x00>((int)qblk.w)); break;
+        case 1: src = make_uint4(dpp<0x55>((int)qblk.x), dpp<0x55>((int)qblk.y), dpp<0x55>((int)qblk.z), dpp<0x55>((int)qblk.w)); break;
+        case 2: src = make_uint4(dpp<0xAA>((int)qblk.x), dpp<0xAA>((int)qblk.y), dpp<0xAA>((int)qblk.z), dpp<0xAA>((int)qblk.w)); break;
+        default: src = make_uint4(dpp<0xFF>((int)qblk.x), dpp<0xFF>((int)qblk.y), dpp<0xFF>((int)qblk.z), dpp<0xFF>((int)qblk.w)); break;
+      }
+      rbits = word(src, i & 3);
+    } else {
+      rbits = word(stream_block(A.C.key0, A.C.key1, env_id, A.t0 + (uint32_t)t, kPolicy,
+                                (uint32_t)(i >> 2), 0u), i & 3);
+    }
+    const float u = unit24(rbits);
     int action = 4;
     float cdf = 0.f;
     const float inv_tot = 1.0f / tot;

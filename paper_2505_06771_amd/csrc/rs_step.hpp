@@ -96,10 +96,14 @@ __device__ void place_points(const SimConst<T> &C, uint32_t env_id, uint32_t epi
   }
 }
 
-// Reset sampler for the group's environment (episode `episode`).
+// Reset sampler for the group's environment (episode `episode`). Kept out of
+// line: it is the cold path of a step, and inlined it would hold registers
+// across the whole step loop. The constants are taken by value: a reference
+// would make the kernel keep its whole argument block in scratch memory.
 template <typename T, int G>
-__device__ void reset_env(const SimConst<T> &C, uint32_t env_id, uint32_t episode, int i, int N,
-                          int lane, T &x, T &y, T &th, T &gx, T &gy) {
+__device__ __attribute__((noinline)) void reset_env(const SimConst<T> C, uint32_t env_id,
+                                                    uint32_t episode, int i, int N, int lane, T &x,
+                                                    T &y, T &th, T &gx, T &gy) {
   int64_t X, Y, GX, GY;
   place_points<T, G>(C, env_id, episode, kPose, i, N, lane, X, Y);
   place_points<T, G>(C, env_id, episode, kGoal, i, N, lane, GX, GY);

@@ -114,8 +114,10 @@ def test_reset_parity(orc, n, kind):
         np.testing.assert_array_equal(x[e], ox.astype(ndt))
         np.testing.assert_array_equal(gy[e], ogy.astype(ndt))
         assert angle_diff(th[e], oth).max() <= (1e-6 if kind == "f32" else 1e-12)
+        # FP32 observations carry cos/sin from the hardware sine (~1e-6): the
+        # observation tolerance of the step tests applies
         np.testing.assert_allclose(ob[e], orc.observe(ox, oy, oth, ogx, ogy),
-                                   atol=1e-6 if kind == "f32" else 1e-12, rtol=0)
+                                   atol=1e-5 if kind == "f32" else 1e-12, rtol=0)
 
 
 def _step_compare(orc, po, R, ctx, p, b, n, steps, t0, tol, explicit_actions=False):
