@@ -182,9 +182,9 @@ template <int B, int E, typename F> __device__ __forceinline__ void static_for(F
 
 // Per-launch constants of the simulation, in the state precision T.
 template <typename T> struct SimConst {
-  T x_min, x_max, y_min, y_max;
-  T dt, l, inv_l, gamma, rs2, kb, half, vmax, aspeed, kp;
-  T R, L, wheel_lim;  // R <= 0: no saturation
+  T xwl, xwh, ywl, ywh;  // walls pulled in by r_s/2: x_min + r_s/2, x_max - r_s/2, ...
+  T dt, l, inv_l, gamma, rs2, kb, vmax, vmax4, aspeed, kp;
+  T R, halfL, wheel_lim;  // R <= 0: no saturation; halfL = L/2
   T inv_R, R_over_L;  // 1/R and R/L
   T goal_r;
   T tol_add;          // active-set admission threshold (normalised violation)

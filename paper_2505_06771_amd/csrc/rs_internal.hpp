@@ -11,7 +11,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/robostep.h"
+#include "robostep.h"
 #include "rs_device.hpp"
 
 namespace rs {
@@ -84,23 +84,23 @@ rs_status check_params(const rs_params *p);
 
 template <typename T> SimConst<T> make_const(const rs_params &p) {
   SimConst<T> C;
-  C.x_min = (T)p.x_min;
-  C.x_max = (T)p.x_max;
-  C.y_min = (T)p.y_min;
-  C.y_max = (T)p.y_max;
+  C.xwl = (T)(p.x_min + 0.5 * p.safety_radius);
+  C.xwh = (T)(p.x_max - 0.5 * p.safety_radius);
+  C.ywl = (T)(p.y_min + 0.5 * p.safety_radius);
+  C.ywh = (T)(p.y_max - 0.5 * p.safety_radius);
   C.dt = (T)p.dt;
   C.l = (T)p.proj_dist;
   C.inv_l = (T)(1.0 / p.proj_dist);
   C.gamma = (T)p.barrier_gain;
   C.rs2 = (T)(p.safety_radius * p.safety_radius);
   C.kb = (T)(p.boundary_gain_factor * p.barrier_gain);
-  C.half = (T)(0.5 * p.safety_radius);
   C.vmax = (T)p.v_max;
+  C.vmax4 = (T)(4.0 * p.v_max);
   C.aspeed = (T)p.action_speed;
   C.kp = (T)p.kp;
   const bool sat = p.wheel_radius > 0.0 && p.base_length > 0.0;
   C.R = sat ? (T)p.wheel_radius : T(0);
-  C.L = sat ? (T)p.base_length : T(1);
+  C.halfL = sat ? (T)(0.5 * p.base_length) : T(0);
   C.wheel_lim = sat ? (T)(p.v_max / p.wheel_radius) : T(0);
   C.inv_R = sat ? (T)(1.0 / p.wheel_radius) : T(0);
   C.R_over_L = sat ? (T)(p.wheel_radius / p.base_length) : T(0);

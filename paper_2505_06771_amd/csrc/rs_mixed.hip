@@ -50,6 +50,9 @@ __device__ void run_tile(const RunArgs &A, char *wave_lds, int lane, int first, 
   int nsteps = A.steps;
   if (A.steps_per_env) nsteps = min(nsteps, A.steps_per_env[e]);
   const int64_t tb = A.t_start ? A.t_start[e] : (int64_t)A.t0;
+  // complete the loads before the step loop (see k_rollout: the in-loop wait
+  // would otherwise also wait for the loop's own stores)
+  __builtin_amdgcn_s_waitcnt(0);
   float s, c;
   sincos_t(th, &s, &c);
   float rsum = 0.f;

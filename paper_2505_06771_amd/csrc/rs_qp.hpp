@@ -71,8 +71,8 @@ template <> __device__ __forceinline__ double big_v<double>() { return 1.0e300; 
 template <typename T>
 __device__ __forceinline__ void wall_bounds(const SimConst<T> &C, T px, T py, T &lox, T &hix,
                                             T &loy, T &hiy) {
-  const T mxh = C.x_max - C.half - px, mxl = px - C.x_min - C.half;
-  const T myh = C.y_max - C.half - py, myl = py - C.y_min - C.half;
+  const T mxh = C.xwh - px, mxl = px - C.xwl;
+  const T myh = C.ywh - py, myl = py - C.ywl;
   hix = tmin(C.vmax, C.kb * (mxh * mxh * mxh));
   lox = tmax(-C.vmax, -(C.kb * (mxl * mxl * mxl)));
   hiy = tmin(C.vmax, C.kb * (myh * myh * myh));
@@ -117,7 +117,7 @@ struct QPInfo {
 // return (ux, uy) is the command; for status 1 it is the per-coordinate
 // fallback. Used when the register-resident solver below runs out of slots.
 template <typename T, int G>
-__device__ __attribute__((noinline)) QPInfo qp_solve_lds(QPScratch<T, G> *sh, const SimConst<T> C, int lane, int i, int N,
+__device__ QPInfo qp_solve_lds(QPScratch<T, G> *sh, const SimConst<T> C, int lane, int i, int N,
                            bool on, T px, T py, T uhx, T uhy, T lox, T hix, T loy, T hiy, T &ux,
                            T &uy) {
   const int base = lane & ~(G - 1);
@@ -174,7 +174,7 @@ __device__ __attribute__((noinline)) QPInfo qp_solve_lds(QPScratch<T, G> *sh, co
         const T d2 = dx * dx + dy * dy;
         const T h = d2 - C.rs2;
         const T bb = C.gamma * (h * h * h);
-        if (T(4) * C.vmax * (tabs(dx) + tabs(dy)) > bb) {
+        if (C.vmax4 * (tabs(dx) + tabs(dy)) > bb) {
           const T dux = ia ? uxj - ux : ux - uxj;  // u_b - u_a
           const T duy = ia ? uyj - uy : uy - uyj;
           const T s = T(2) * (dx * dux + dy * duy) - bb;
@@ -400,7 +400,7 @@ namespace rs {
 // When a row must enter while all slots are taken, or the Gram system loses
 // positive definiteness, the general solver restarts from scratch.
 // ---------------------------------------------------------------------------
-constexpr int kQR = 4;
+constexpr int kQR = 3;
 
 template <typename T> struct QPActive {
   int q;
@@ -465,7 +465,7 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, const SimConst<T> &C, int lane, 
     const T d2 = dx * dx + dy * dy;
     const T h = d2 - C.rs2;
     const T bb = C.gamma * (h * h * h);
-    const bool cand = valid && (T(4) * C.vmax * (tabs(dx) + tabs(dy)) > bb);
+    const bool cand = valid && (C.vmax4 * (tabs(dx) + tabs(dy)) > bb);
     cdx[K - 1] = dx;
     cdy[K - 1] = dy;
     cb[K - 1] = bb;

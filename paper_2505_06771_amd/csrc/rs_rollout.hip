@@ -117,6 +117,12 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
 #pragma unroll
   for (int j = 0; j < 4; ++j) b3f[j] = (4 * g + j) < 5 ? A.b3[4 * g + j] : 0.0f;
 
+  // Complete the state and weight loads before the step loop. Without this
+  // the first in-loop use waits on the vector-memory counter, which on this
+  // architecture also counts the loop's own global stores: every step would
+  // stall until its observation stores had landed.
+  __builtin_amdgcn_s_waitcnt(0);
+
   float *obs_w = obs_lds[wave];
   float4 *logit_w = logit_lds[wave];
   QPScratch<float, G> *sh = &qs[threadIdx.x / G];
@@ -130,14 +136,16 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
     // ---- 1. observation -> LDS (packed) -> HBM --------------------------
     float *o = obs_w + row * D;
     if (on) { o[0] = x; o[1] = y; o[2] = c; o[3] = s; }
-    for (int j = 0; j < N; ++j) {
-      const float xj = __shfl(x, base + j, 64), yj = __shfl(y, base + j, 64);
-      if (on && j != i) {
+    static_for<1, G>([&](auto kc) {  // neighbour (i + K) mod G by DPP rotation
+      constexpr int K = decltype(kc)::value;
+      const float xj = grot<G, K>(x, lane), yj = grot<G, K>(y, lane);
+      const int j = (i + K) & (G - 1);
+      if (on && j < N) {
         const int m = 4 + 2 * (j < i ? j : j - 1);
         o[m] = xj - x;
         o[m + 1] = yj - y;
       }
-    }
+    });
     if (on) { o[D - 2] = gx - x; o[D - 1] = gy - y; }
     wave_lds_sync();
     if (A.obs) {

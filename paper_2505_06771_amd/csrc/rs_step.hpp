@@ -37,9 +37,8 @@ __device__ __forceinline__ void si_to_uni(const SimConst<T> &C, T c, T s, T ux, 
   v = c * ux + s * uy;
   w = (c * uy - s * ux) * C.inv_l;
   if (C.R > T(0)) {
-    const T halfL = T(0.5) * C.L;
-    T phr = (v + halfL * w) * C.inv_R;
-    T phl = (v - halfL * w) * C.inv_R;
+    T phr = (v + C.halfL * w) * C.inv_R;
+    T phl = (v - C.halfL * w) * C.inv_R;
     phr = tmin(tmax(phr, -C.wheel_lim), C.wheel_lim);
     phl = tmin(tmax(phl, -C.wheel_lim), C.wheel_lim);
     v = T(0.5) * C.R * (phr + phl);
@@ -101,7 +100,7 @@ __device__ void place_points(const SimConst<T> &C, uint32_t env_id, uint32_t epi
 // across the whole step loop. The constants are taken by value: a reference
 // would make the kernel keep its whole argument block in scratch memory.
 template <typename T, int G>
-__device__ __attribute__((noinline)) void reset_env(const SimConst<T> C, uint32_t env_id,
+__device__ void reset_env(const SimConst<T> C, uint32_t env_id,
                                                     uint32_t episode, int i, int N, int lane, T &x,
                                                     T &y, T &th, T &gx, T &gy) {
   int64_t X, Y, GX, GY;
