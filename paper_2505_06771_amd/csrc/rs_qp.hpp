@@ -59,9 +59,25 @@ __device__ __forceinline__ int pair_index(int a, int b, int N) {
   return a * (2 * N - a - 1) / 2 + (b - a - 1);
 }
 
-template <typename T> __device__ __forceinline__ T tmax(T a, T b) { return a > b ? a : b; }
-template <typename T> __device__ __forceinline__ T tmin(T a, T b) { return a < b ? a : b; }
-template <typename T> __device__ __forceinline__ T tabs(T a) { return a < T(0) ? -a : a; }
+// min / max / |.| as single instructions (operands are never NaN here).
+__device__ __forceinline__ float tmax(float a, float b) { return __builtin_fmaxf(a, b); }
+__device__ __forceinline__ float tmin(float a, float b) { return __builtin_fminf(a, b); }
+__device__ __forceinline__ double tmax(double a, double b) { return __builtin_fmax(a, b); }
+__device__ __forceinline__ double tmin(double a, double b) { return __builtin_fmin(a, b); }
+// clamp to [lo, hi] with lo <= hi: one median-of-three in FP32
+__device__ __forceinline__ float tclamp(float x, float lo, float hi) {
+  return __builtin_amdgcn_fmed3f(x, lo, hi);
+}
+__device__ __forceinline__ double tclamp(double x, double lo, double hi) {
+  return __builtin_fmin(__builtin_fmax(x, lo), hi);
+}
+__device__ __forceinline__ float tabs(float a) { return __builtin_fabsf(a); }
+__device__ __forceinline__ double tabs(double a) { return __builtin_fabs(a); }
+// Quotient used by the step-length and ratio tests of the solver: in FP32 a
+// reciprocal (1 ulp) times the numerator, in FP64 the correctly rounded
+// division.
+__device__ __forceinline__ float qdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double qdiv(double a, double b) { return a / b; }
 template <typename T> __device__ __forceinline__ T big_v();
 template <> __device__ __forceinline__ float big_v<float>() { return 3.0e38f; }
 template <> __device__ __forceinline__ double big_v<double>() { return 1.0e300; }
@@ -295,16 +311,16 @@ __device__ QPInfo qp_solve_lds(QPScratch<T, G> *sh, const SimConst<T> C, int lan
       for (int a = 0; a < q; ++a) {
         const T ra = sh->rv[a];
         if (ra > C.eps_r) {
-          const T ratio = sh->lam[a] / ra;
+          const T ratio = qdiv(sh->lam[a], ra);
           if (ratio < t1) { t1 = ratio; drop = a; }
         }
       }
       if (on && fx != 0 && rfx > C.eps_r) {
-        const T ratio = mux / rfx;
+        const T ratio = qdiv(mux, rfx);
         if (ratio < t1 || (ratio == t1 && drop < 0)) { t1 = ratio; drop = 1024 + 2 * i; }
       }
       if (on && fy != 0 && rfy > C.eps_r) {
-        const T ratio = muy / rfy;
+        const T ratio = qdiv(muy, rfy);
         if (ratio < t1 || (ratio == t1 && drop < 0)) { t1 = ratio; drop = 1024 + 2 * i + 1; }
       }
       group_argmin<G>(t1, drop);
@@ -319,7 +335,7 @@ __device__ QPInfo qp_solve_lds(QPScratch<T, G> *sh, const SimConst<T> C, int lan
         sp = __shfl(mine, base + pa, 64);
       }
       const bool z_ok = zz > C.eps_z * cpn2;
-      const T t2 = z_ok ? sp / zz : BIG;
+      const T t2 = z_ok ? qdiv(sp, zz) : BIG;
       if (drop < 0 && !z_ok) { dead = true; break; }  // no step can restore p
       const bool full = z_ok && (drop < 0 || t2 <= t1);
       const T t = full ? t2 : t1;
@@ -650,16 +666,16 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, const SimConst<T> &C, int lane, 
 #pragma unroll
       for (int a = 0; a < kQR; ++a) {
         if (a < q && rv[a] > C.eps_r) {
-          const T ratio = slam[a] / rv[a];
+          const T ratio = qdiv(slam[a], rv[a]);
           if (ratio < t1) { t1 = ratio; drop = a; }
         }
       }
       if (on && fx != 0 && rfx > C.eps_r) {
-        const T ratio = mux / rfx;
+        const T ratio = qdiv(mux, rfx);
         if (ratio < t1 || (ratio == t1 && drop < 0)) { t1 = ratio; drop = 1024 + 2 * i; }
       }
       if (on && fy != 0 && rfy > C.eps_r) {
-        const T ratio = muy / rfy;
+        const T ratio = qdiv(muy, rfy);
         if (ratio < t1 || (ratio == t1 && drop < 0)) { t1 = ratio; drop = 1024 + 2 * i + 1; }
       }
       gargmin<G>(t1, drop);
@@ -675,7 +691,7 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, const SimConst<T> &C, int lane, 
       }
       const T sp = gsum<G>(contrib) - (p_pair ? bp : T(0));
       const bool z_ok = zz > C.eps_z * cpn2;
-      const T t2 = z_ok ? sp / zz : BIG;
+      const T t2 = z_ok ? qdiv(sp, zz) : BIG;
       if (drop < 0 && !z_ok) { dead = true; break; }
       const bool full = z_ok && (drop < 0 || t2 <= t1);
       const T t = full ? t2 : t1;

@@ -26,6 +26,7 @@
 namespace rs {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short shortx8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kRollBlock = 256;
@@ -51,13 +52,24 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// ReLU of eight bf16 values with packed 16-bit integer max: a bf16 with the
+// sign bit set is a negative int16, so max(., 0) zeroes exactly the negative
+// values (and -0). Rounding commutes with ReLU, so this equals rounding the
+// FP32 ReLU.
+__device__ __forceinline__ bf16x8 relu_bf16x8(bf16x8 v) {
+  const shortx8 z = {0, 0, 0, 0, 0, 0, 0, 0};
+  return __builtin_bit_cast(bf16x8, __builtin_elementwise_max(__builtin_bit_cast(shortx8, v), z));
+}
+
 // Hidden index held in slot j of lane group g at k-step s of layers 2 and 3:
 // the accumulator of output tile (2s + j/4), register j%4, of lane group g.
 __device__ __forceinline__ int perm_hidden(int s, int g, int j) {
   return 16 * (2 * s + (j >> 2)) + 4 * g + (j & 3);
 }
 
-template <int G>
+// NC > 0 fixes the robot count at compile time (NC <= G); NC = 0 reads it
+// from the arguments.
+template <int G, int NC>
 __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
   constexpr int EPW = 64 / G;
   __shared__ QPScratch<float, G> qs[kRollBlock / G];
@@ -80,7 +92,8 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
   const int e0 = (blockIdx.x * kRollWaves + wave) * EPW;
   if (e0 >= A.E) return;  // the whole wavefront leaves together
   const int e = e0 + grp;
-  const int N = A.N, D = A.D;
+  const int N = NC ? NC : A.N;
+  const int D = 2 * N + 4;
   const bool env_ok = e < A.E;
   const bool on = env_ok && i < N;
   const int nenv = min(EPW, A.E - e0);
@@ -124,6 +137,14 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
   __builtin_amdgcn_s_waitcnt(0);
 
   float *obs_w = obs_lds[wave];
+  // Zero the wavefront's staging area once: the MLP reads eight features per
+  // lane from packed rows without bounds tests, so what it reads past the
+  // last row (multiplied by zero weights, or feeding columns of robots that
+  // do not exist) must be finite.
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+    reinterpret_cast<float4 *>(obs_w)[q * 64 + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+  wave_lds_sync();
   float4 *logit_w = logit_lds[wave];
   QPScratch<float, G> *sh = &qs[threadIdx.x / G];
   const int base = lane & ~(G - 1);
@@ -164,13 +185,23 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
     for (int nt = 0; nt < 4; ++nt) {
       const int n = 16 * nt + c16;  // wave lane of the robot in this column
       const int ng = n / G, ni = n & (G - 1);
-      const bool nvalid = ni < N && ng < nenv;
-      const float *src = obs_w + (ng * N + ni) * D;
+      // features 8g .. 8g+7 of robot n; past D they run into the next row
+      // (finite, times zero weights); lanes of missing robots read finite
+      // rows whose logits are never used
+      const float *src = obs_w + (ng * N + ni) * D + 8 * g;
       bf16x8 xb;
+      if ((D & 3) == 0) {
+        const float4 f0 = reinterpret_cast<const float4 *>(src)[0];
+        const float4 f1 = reinterpret_cast<const float4 *>(src)[1];
+        xb[0] = (__bf16)f0.x; xb[1] = (__bf16)f0.y; xb[2] = (__bf16)f0.z; xb[3] = (__bf16)f0.w;
+        xb[4] = (__bf16)f1.x; xb[5] = (__bf16)f1.y; xb[6] = (__bf16)f1.z; xb[7] = (__bf16)f1.w;
+      } else {
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int f = 8 * g + j;
-        xb[j] = (nvalid && f < D) ? (__bf16)src[f] : zero;
+        for (int j = 0; j < 4; ++j) {
+          const float2 f = reinterpret_cast<const float2 *>(src)[j];
+          xb[2 * j] = (__bf16)f.x;
+          xb[2 * j + 1] = (__bf16)f.y;
+        }
       }
       floatx4 h1[4];
 #pragma unroll
@@ -181,9 +212,11 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
       }
       bf16x8 hb[2];
 #pragma unroll
-      for (int sk = 0; sk < 2; ++sk)
+      for (int sk = 0; sk < 2; ++sk) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) hb[sk][j] = (__bf16)fmaxf(h1[2 * sk + (j >> 2)][j & 3], 0.0f);
+        for (int j = 0; j < 8; ++j) hb[sk][j] = (__bf16)h1[2 * sk + (j >> 2)][j & 3];
+        hb[sk] = relu_bf16x8(hb[sk]);
+      }
       floatx4 h2[4];
 #pragma unroll
       for (int mo = 0; mo < 4; ++mo) {
@@ -194,9 +227,11 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
       }
       bf16x8 hc[2];
 #pragma unroll
-      for (int sk = 0; sk < 2; ++sk)
+      for (int sk = 0; sk < 2; ++sk) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) hc[sk][j] = (__bf16)fmaxf(h2[2 * sk + (j >> 2)][j & 3], 0.0f);
+        for (int j = 0; j < 8; ++j) hc[sk][j] = (__bf16)h2[2 * sk + (j >> 2)][j & 3];
+        hc[sk] = relu_bf16x8(hc[sk]);
+      }
       floatx4 lg = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3f[0], hc[0], b3f, 0, 0, 0);
       lg = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3f[1], hc[1], lg, 0, 0, 0);
       // lane (g, c16) holds logits 4g..4g+3 of robot n
@@ -240,7 +275,7 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
     const float u = unit24(rbits);
     int action = 4;
     float cdf = 0.f;
-    const float inv_tot = 1.0f / tot;
+    const float inv_tot = __builtin_amdgcn_rcpf(tot);
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
       cdf += ex[k] * inv_tot;
@@ -263,24 +298,22 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
   if (env_ok && i == 0) { A.step[e] = step; A.episode[e] = episode; }
 }
 
-static const void *rollout_kernel(int G) {
-  switch (G) {
-    case 2: return reinterpret_cast<const void *>(&k_rollout<2>);
-    case 4: return reinterpret_cast<const void *>(&k_rollout<4>);
-    case 8: return reinterpret_cast<const void *>(&k_rollout<8>);
-    default: return reinterpret_cast<const void *>(&k_rollout<16>);
+// Kernel for N robots: a compile-time robot count for N = 8 (8 lanes, no
+// idle lane), the lane-group width with a run-time count otherwise.
+static const void *rollout_kernel(int N) {
+  if (N == 8) return reinterpret_cast<const void *>(&k_rollout<8, 8>);
+  switch (pow2_group(N)) {
+    case 2: return reinterpret_cast<const void *>(&k_rollout<2, 0>);
+    case 4: return reinterpret_cast<const void *>(&k_rollout<4, 0>);
+    case 8: return reinterpret_cast<const void *>(&k_rollout<8, 0>);
+    default: return reinterpret_cast<const void *>(&k_rollout<16, 0>);
   }
 }
 
 static bool launch_rollout(const RolloutArgs &A, dim3 grid, hipStream_t st) {
-  const int G = pow2_group(A.N);
-  switch (G) {
-    case 2: hipLaunchKernelGGL(k_rollout<2>, grid, dim3(kRollBlock), 0, st, A); break;
-    case 4: hipLaunchKernelGGL(k_rollout<4>, grid, dim3(kRollBlock), 0, st, A); break;
-    case 8: hipLaunchKernelGGL(k_rollout<8>, grid, dim3(kRollBlock), 0, st, A); break;
-    default: hipLaunchKernelGGL(k_rollout<16>, grid, dim3(kRollBlock), 0, st, A); break;
-  }
-  return hipGetLastError() == hipSuccess;
+  RolloutArgs copy = A;
+  void *kargs[] = {&copy};
+  return hipLaunchKernel(rollout_kernel(A.N), grid, dim3(kRollBlock), kargs, 0, st) == hipSuccess;
 }
 
 }  // namespace rs
@@ -372,7 +405,7 @@ extern "C" rs_status rollout(rs_ctx *ctx, const rs_params *p, const rs_batch *b,
     void *kargs[] = {&copy};
     hipKernelNodeParams kp;
     std::memset(&kp, 0, sizeof(kp));
-    kp.func = const_cast<void *>(rollout_kernel(G));
+    kp.func = const_cast<void *>(rollout_kernel(A.N));
     kp.gridDim = grid;
     kp.blockDim = dim3(kRollBlock);
     kp.sharedMemBytes = 0;

@@ -39,8 +39,8 @@ __device__ __forceinline__ void si_to_uni(const SimConst<T> &C, T c, T s, T ux, 
   if (C.R > T(0)) {
     T phr = (v + C.halfL * w) * C.inv_R;
     T phl = (v - C.halfL * w) * C.inv_R;
-    phr = tmin(tmax(phr, -C.wheel_lim), C.wheel_lim);
-    phl = tmin(tmax(phl, -C.wheel_lim), C.wheel_lim);
+    phr = tclamp(phr, -C.wheel_lim, C.wheel_lim);
+    phl = tclamp(phl, -C.wheel_lim, C.wheel_lim);
     v = T(0.5) * C.R * (phr + phl);
     w = C.R_over_L * (phr - phl);
   }
