@@ -503,18 +503,23 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, const SimConst<T> &C, int lane, 
     else if (uhy < loy) { uy = loy; fy = -1; muy = loy - uhy; }
   }
 
+  // Active pairwise rows: group-uniform slots (robots, multiplier) and, per
+  // lane, the row's coefficients at the lane's robot (zero unless the robot is
+  // one of the row's two ends). Gram entries and the products with the
+  // entering row are then one butterfly sum each.
   int q = 0;
   int sa[kQR], sb[kQR];
-  T sdx[kQR], sdy[kQR], slam[kQR];
-  // Cholesky factor of the Gram system of the active rows, kept across
+  T slam[kQR], ccx[kQR], ccy[kQR];
+  // Cholesky factor of the Gram system over the free coordinates, kept across
   // iterations: a row entering by a full step appends [w, |z|] (since
-  // |z|^2 = c_p^T c_p - |L^-1 g|^2); any other change refactors.
+  // |z|^2 = c_p^T c_p - |L^-1 g|^2); any change of the free set or a dropped
+  // row refactors.
   T L[kQR * (kQR + 1) / 2], Linv[kQR];
   bool lvalid = true;
 #pragma unroll
   for (int a = 0; a < kQR; ++a) {
     sa[a] = sb[a] = -1;
-    sdx[a] = sdy[a] = slam[a] = T(0);
+    slam[a] = ccx[a] = ccy[a] = T(0);
     Linv[a] = T(0);
 #pragma unroll
     for (int b = 0; b <= a; ++b) L[tri(a, b)] = T(0);
@@ -523,30 +528,29 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, const SimConst<T> &C, int lane, 
   const int cap = C.qp_cap > 0 ? C.qp_cap : 8 * N + 32;
   bool restart = false;
 
-  while (!dead) {
-    // --- most violated constraint (argmax carries the row's data) ----------
+  // --- one-row fast path -----------------------------------------------------
+  // Every bound holds at the box clip. When exactly one pairwise row p (robots
+  // a < b) is violated there, the projection onto box & {c_p.u <= b_p} has a
+  // closed form: u(l) = clip(u_nom - l c_p), where l >= 0 is the root of the
+  // non-increasing, piecewise linear phi(l) = c_p.u(l) - b_p, whose breakpoints
+  // are where a coordinate of robot a or b meets a bound. Only robots a and b
+  // move, so when every row through a or b holds at u(l), u(l) satisfies the
+  // whole problem; as the minimiser over a superset of its feasible set it is
+  // the solution. Otherwise u(l), with p active and the clipped coordinates
+  // fixed, is a dual-feasible start for the active-set loop below.
+  bool run_gi = !dead;
+  if (!dead) {
     T best = C.tol_add, bdx = T(0), bdy = T(0), bbb = T(0);
-    int bid = -1;
-    if (on) {
-      if (fx == 0) {
-        const T su = ux - hix, sl = lox - ux;
-        if (su > best) { best = su; bid = 256 + 4 * i; }
-        else if (sl > best) { best = sl; bid = 256 + 4 * i + 1; }
-      }
-      if (fy == 0) {
-        const T su = uy - hiy, sl = loy - uy;
-        if (su > best) { best = su; bid = 256 + 4 * i + 2; }
-        else if (sl > best) { best = sl; bid = 256 + 4 * i + 3; }
-      }
-    }
+    int bid = -1, nviol = 0;
     static_for<1, KH + 1>([&](auto kc) {
       constexpr int K = decltype(kc)::value;
       const T uxj = grot<G, K>(ux, lane), uyj = grot<G, K>(uy, lane);
-      if (cpid[K - 1] >= 0 && !((own_act >> K) & 1u)) {
+      if (cpid[K - 1] >= 0) {
         const bool ia = i < ((i + K) & (G - 1));
         const T dux = ia ? uxj - ux : ux - uxj;
         const T duy = ia ? uyj - uy : uy - uyj;
         const T sn = (T(2) * (cdx[K - 1] * dux + cdy[K - 1] * duy) - cb[K - 1]) * crn[K - 1];
+        nviol += sn > C.tol_add ? 1 : 0;
         if (sn > best) {
           best = sn;
           bid = cpid[K - 1];
@@ -557,208 +561,324 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, const SimConst<T> &C, int lane, 
       }
     });
     gargmax_payload<G>(best, bid, bdx, bdy, bbb);
-    if (bid < 0) break;  // optimal
-    if (++info.iters > cap) { info.status = 2; break; }
-
-    const bool p_pair = bid < 256;
-    const int pa = p_pair ? (bid >> 4) : ((bid - 256) >> 2);
-    const int pb = p_pair ? (bid & 15) : -1;
-    const int pk = p_pair ? 0 : (((bid - 256) >> 1) & 1);
-    const int psig = p_pair ? 0 : (((bid - 256) & 1) ? -1 : 1);
-    const T dpx = bdx, dpy = bdy, bp = bbb;
-    T lam_p = T(0);
-    bool added = false;
-    for (int inner = 0; inner < cap && !added; ++inner) {
-      const uint32_t freex = ~group_bits<G>(__ballot(fx != 0), lane);
-      const uint32_t freey = ~group_bits<G>(__ballot(fy != 0), lane);
-      T rv[kQR], w[kQR];
+    const int nv = gsum<G>(nviol);
+    if (bid < 0) {
+      run_gi = false;  // the box clip is the solution
+    } else if (nv == 1) {
+      const int gbase = lane & ~(G - 1);
+      const int pa = bid >> 4, pb = bid & 15;
+      const int la = gbase + pa, lb = gbase + pb;
+      // coordinates 0..3 = (a.x, a.y, b.x, b.y) and their row coefficients
+      const T cc[4] = {T(-2) * bdx, T(-2) * bdy, T(2) * bdx, T(2) * bdy};
+      const T un[4] = {__shfl(uhx, la, 64), __shfl(uhy, la, 64), __shfl(uhx, lb, 64),
+                       __shfl(uhy, lb, 64)};
+      const T lo[4] = {__shfl(lox, la, 64), __shfl(loy, la, 64), __shfl(lox, lb, 64),
+                       __shfl(loy, lb, 64)};
+      const T hi[4] = {__shfl(hix, la, 64), __shfl(hiy, la, 64), __shfl(hix, lb, 64),
+                       __shfl(hiy, lb, 64)};
+      T e1[4], e2[4];  // multiplier values where coordinate k meets hi_k / lo_k
 #pragma unroll
-      for (int a = 0; a < kQR; ++a) { rv[a] = T(0); w[a] = T(0); }
-      if (q > 0) {
-        if (!lvalid) {
-          // refactor the Gram system over the current free coordinates
-          bool pd = true;
+      for (int k = 0; k < 4; ++k) {
+        const T r = cc[k] != T(0) ? qdiv(T(1), cc[k]) : T(0);
+        e1[k] = (un[k] - hi[k]) * r;
+        e2[k] = (un[k] - lo[k]) * r;
+      }
+      auto phi = [&](T lm) {
+        T acc = -bbb;
 #pragma unroll
-          for (int a = 0; a < kQR; ++a) {
-            if (a < q) {
+        for (int k = 0; k < 4; ++k) acc += cc[k] * tclamp(un[k] - lm * cc[k], lo[k], hi[k]);
+        return acc;
+      };
+      // largest breakpoint (or 0) where phi is still positive
+      T llo = T(0), plo = phi(T(0));
 #pragma unroll
-              for (int b = 0; b <= a; ++b) {
-                T sgm = gram_entry<T>(sa[a], sb[a], sdx[a], sdy[a], sa[b], sb[b], sdx[b], sdy[b],
-                                      freex, freey);
+      for (int k = 0; k < 4; ++k) {
+        const T p1 = phi(e1[k]), p2 = phi(e2[k]);
+        if (p1 > T(0) && e1[k] > llo) { llo = e1[k]; plo = p1; }
+        if (p2 > T(0) && e2[k] > llo) { llo = e2[k]; plo = p2; }
+      }
+      // slope of -phi just right of llo: coordinates still free there
+      T slope = T(0);
 #pragma unroll
-                for (int k2 = 0; k2 < b; ++k2) sgm -= L[tri(a, k2)] * L[tri(b, k2)];
-                if (b == a) {
-                  pd = pd && (sgm > T(0));
-                  const T rs = sgm > T(0) ? rsqrt_t(sgm) : T(0);
-                  L[tri(a, a)] = sgm * rs;
-                  Linv[a] = rs;
-                } else {
-                  L[tri(a, b)] = sgm * Linv[b];
-                }
-              }
-            }
-          }
-          if (!pd) { restart = true; break; }
-          lvalid = true;
+      for (int k = 0; k < 4; ++k) {
+        const bool fr = cc[k] != T(0) && tmin(e1[k], e2[k]) <= llo && llo < tmax(e1[k], e2[k]);
+        slope += fr ? cc[k] * cc[k] : T(0);
+      }
+      if (slope > T(0)) {
+        const T lam = tmax(llo + qdiv(plo, slope), T(0));
+        T uu[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) uu[k] = tclamp(un[k] - lam * cc[k], lo[k], hi[k]);
+        // rows through a or b, in the scan's normalised form
+        const T pxa = __shfl(px, la, 64), pya = __shfl(py, la, 64);
+        const T pxb = __shfl(px, lb, 64), pyb = __shfl(py, lb, 64);
+        bool bad = false;
+        if (on && i != pa && i != pb) {
+          auto row_viol = [&](T pxr, T pyr, T uxr, T uyr) {
+            const T dx = pxr - px, dy = pyr - py;
+            const T d2 = dx * dx + dy * dy;
+            const T h = d2 - C.rs2;
+            const T sn = T(2) * (dx * (ux - uxr) + dy * (uy - uyr)) - C.gamma * (h * h * h);
+            return d2 > T(0) ? sn * (T(0.35355339059327373) * rsqrt_t(d2)) : sn;
+          };
+          bad = row_viol(pxa, pya, uu[0], uu[1]) > C.tol_add ||
+                row_viol(pxb, pyb, uu[2], uu[3]) > C.tol_add;
         }
-        // g = C_S^free c_p, then w = L^-1 g and r = L^-T w
-#pragma unroll
-        for (int a = 0; a < kQR; ++a) {
-          if (a < q) {
-            T g;
-            if (p_pair) {
-              g = gram_entry<T>(sa[a], sb[a], sdx[a], sdy[a], pa, pb, dpx, dpy, freex, freey);
-            } else {
-              const T comp = pk ? sdy[a] : sdx[a];
-              g = (pa == sa[a]) ? T(-2) * comp : ((pa == sb[a]) ? T(2) * comp : T(0));
-              g *= T(psig);
-            }
-#pragma unroll
-            for (int k2 = 0; k2 < a; ++k2) g -= L[tri(a, k2)] * w[k2];
-            w[a] = g * Linv[a];
-          }
-        }
-#pragma unroll
-        for (int a = kQR - 1; a >= 0; --a) {
-          if (a < q) {
-            T sgm = w[a];
-#pragma unroll
-            for (int k2 = a + 1; k2 < kQR; ++k2)
-              if (k2 < q) sgm -= L[tri(k2, a)] * rv[k2];
-            rv[a] = sgm * Linv[a];
-          }
-        }
-      }
-      // (C_S^T r) and c_p at my robot
-      T crx = T(0), cry = T(0);
-#pragma unroll
-      for (int a = 0; a < kQR; ++a) {
-        if (a < q) {
-          if (i == sa[a]) { crx -= T(2) * sdx[a] * rv[a]; cry -= T(2) * sdy[a] * rv[a]; }
-          else if (i == sb[a]) { crx += T(2) * sdx[a] * rv[a]; cry += T(2) * sdy[a] * rv[a]; }
-        }
-      }
-      T cpx = T(0), cpy = T(0);
-      if (p_pair) {
-        if (i == pa) { cpx = T(-2) * dpx; cpy = T(-2) * dpy; }
-        else if (i == pb) { cpx = T(2) * dpx; cpy = T(2) * dpy; }
-      } else if (i == pa) {
-        if (pk) cpy = T(psig); else cpx = T(psig);
-      }
-      if (!on) { crx = cry = cpx = cpy = T(0); }
-      const T zx = fx == 0 ? cpx - crx : T(0);
-      const T zy = fy == 0 ? cpy - cry : T(0);
-      const T rfx = fx != 0 ? T(fx) * (cpx - crx) : T(0);
-      const T rfy = fy != 0 ? T(fy) * (cpy - cry) : T(0);
-      const T zz = gsum<G>(zx * zx + zy * zy);
-      T cpn2 = T(1);
-      if (p_pair) {
-        T sa2 = T(0), sb2 = T(0);
-        if ((freex >> pa) & 1u) sa2 += dpx * dpx;
-        if ((freey >> pa) & 1u) sa2 += dpy * dpy;
-        if ((freex >> pb) & 1u) sb2 += dpx * dpx;
-        if ((freey >> pb) & 1u) sb2 += dpy * dpy;
-        cpn2 = T(4) * (sa2 + sb2);
-      }
-      // blocking step t1 over active rows (uniform) and my fixed bounds
-      T t1 = BIG;
-      int drop = -1;
-#pragma unroll
-      for (int a = 0; a < kQR; ++a) {
-        if (a < q && rv[a] > C.eps_r) {
-          const T ratio = qdiv(slam[a], rv[a]);
-          if (ratio < t1) { t1 = ratio; drop = a; }
-        }
-      }
-      if (on && fx != 0 && rfx > C.eps_r) {
-        const T ratio = qdiv(mux, rfx);
-        if (ratio < t1 || (ratio == t1 && drop < 0)) { t1 = ratio; drop = 1024 + 2 * i; }
-      }
-      if (on && fy != 0 && rfy > C.eps_r) {
-        const T ratio = qdiv(muy, rfy);
-        if (ratio < t1 || (ratio == t1 && drop < 0)) { t1 = ratio; drop = 1024 + 2 * i + 1; }
-      }
-      gargmin<G>(t1, drop);
-      // current violation of p
-      T contrib = T(0);
-      if (on) {
-        if (p_pair) {
-          if (i == pa) contrib = T(-2) * (dpx * ux + dpy * uy);
-          else if (i == pb) contrib = T(2) * (dpx * ux + dpy * uy);
-        } else if (i == pa) {
-          contrib = pk ? (psig > 0 ? uy - hiy : loy - uy) : (psig > 0 ? ux - hix : lox - ux);
-        }
-      }
-      const T sp = gsum<G>(contrib) - (p_pair ? bp : T(0));
-      const bool z_ok = zz > C.eps_z * cpn2;
-      const T t2 = z_ok ? qdiv(sp, zz) : BIG;
-      if (drop < 0 && !z_ok) { dead = true; break; }
-      const bool full = z_ok && (drop < 0 || t2 <= t1);
-      const T t = full ? t2 : t1;
-      if (full && p_pair && q == kQR) { restart = true; break; }  // no slot left
-      if (z_ok) {
-        ux -= t * zx;
-        uy -= t * zy;
-      }
-#pragma unroll
-      for (int a = 0; a < kQR; ++a)
-        if (a < q) slam[a] -= t * rv[a];
-      if (on) {
-        mux -= t * rfx;
-        muy -= t * rfy;
-      }
-      lam_p += t;
-      if (full) {
-        if (p_pair) {
-          // append the row and extend the factor: L[q] = [w, |z|]
-          const T rz = rsqrt_t(zz);
-#pragma unroll
-          for (int a = 0; a < kQR; ++a) {
-            if (a == q) {
-              sa[a] = pa; sb[a] = pb; sdx[a] = dpx; sdy[a] = dpy; slam[a] = lam_p;
-#pragma unroll
-              for (int k2 = 0; k2 < a; ++k2) L[tri(a, k2)] = w[k2];
-              L[tri(a, a)] = zz * rz;
-              Linv[a] = rz;
-            }
-          }
-          ++q;
+        // adopt u(l) with p active; the loop continues from it if needed
+        run_gi = group_any<G>(bad, lane);
+        info.iters = 1;
+        q = 1;
+        sa[0] = pa;
+        sb[0] = pb;
+        slam[0] = lam;
+        lvalid = false;
+        {
           int owner, kk;
           pair_owner_g<G>(pa, pb, owner, kk);
           if (i == owner) own_act |= 1u << kk;
-        } else {
-          if (i == pa) {
-            if (pk) { fy = psig; muy = lam_p; uy = psig > 0 ? hiy : loy; }
-            else { fx = psig; mux = lam_p; ux = psig > 0 ? hix : lox; }
-          }
-          lvalid = false;  // the free coordinates changed
         }
-        added = true;
-      } else if (drop >= 1024) {
-        const int r = (drop - 1024) >> 1, cc = (drop - 1024) & 1;
-        if (i == r) {
-          if (cc) { fy = 0; muy = T(0); } else { fx = 0; mux = T(0); }
+        const bool ma = i == pa, mb = i == pb;
+        ccx[0] = ma ? cc[0] : (mb ? cc[2] : T(0));
+        ccy[0] = ma ? cc[1] : (mb ? cc[3] : T(0));
+        if (ma || mb) {
+          // free or clipped at the multiplier lam: fixed coordinates carry
+          // the bound multiplier that makes the point stationary
+          const T vx = (ma ? un[0] : un[2]) - lam * ccx[0];
+          const T vy = (ma ? un[1] : un[3]) - lam * ccy[0];
+          ux = ma ? uu[0] : uu[2];
+          uy = ma ? uu[1] : uu[3];
+          fx = vx > hix ? 1 : (vx < lox ? -1 : 0);
+          mux = vx > hix ? vx - hix : (vx < lox ? lox - vx : T(0));
+          fy = vy > hiy ? 1 : (vy < loy ? -1 : 0);
+          muy = vy > hiy ? vy - hiy : (vy < loy ? loy - vy : T(0));
         }
-        lvalid = false;
-      } else {
-        int owner = 0, kk = 0;
-#pragma unroll
-        for (int a = 0; a < kQR; ++a)
-          if (a == drop) pair_owner_g<G>(sa[a], sb[a], owner, kk);
-        if (i == owner) own_act &= ~(1u << kk);
-#pragma unroll
-        for (int a = 0; a < kQR - 1; ++a) {
-          if (a >= drop && a + 1 < q) {
-            sa[a] = sa[a + 1]; sb[a] = sb[a + 1];
-            sdx[a] = sdx[a + 1]; sdy[a] = sdy[a + 1]; slam[a] = slam[a + 1];
-          }
-        }
-        --q;
-        lvalid = false;
       }
-      if (++info.iters > cap) { info.status = 2; break; }
     }
-    if (restart || info.status == 2 || dead) break;
+  }
+
+  // --- active-set loop ---------------------------------------------------------
+  // One flat loop. Without a pending row an iteration picks the most violated
+  // row p; with one it takes a step toward satisfying p: a full step makes p
+  // active, a partial step releases the blocking active row or fixed bound.
+  // Unused slots hold zero coefficients and identity rows of the factor, so
+  // the slot algebra runs over all kQR slots as straight-line code.
+  bool pend = false;
+  bool p_pair = false;
+  int pa = 0, pb = 0, pk = 0, psig = 0;
+  T cpx = T(0), cpy = T(0), bp = T(0), lam_p = T(0);
+#pragma unroll
+  for (int a = 0; a < kQR; ++a) {
+    if (a >= q) {
+      L[tri(a, a)] = T(1);
+      Linv[a] = T(1);
+    }
+  }
+  bool go = run_gi && !dead;
+  while (go) {
+    if (!pend) {
+      // --- most violated constraint (argmax carries the row's data) --------
+      T best = C.tol_add, bdx = T(0), bdy = T(0), bbb = T(0);
+      int bid = -1;
+      if (on) {
+        if (fx == 0) {
+          const T su = ux - hix, sl = lox - ux;
+          if (su > best) { best = su; bid = 256 + 4 * i; }
+          else if (sl > best) { best = sl; bid = 256 + 4 * i + 1; }
+        }
+        if (fy == 0) {
+          const T su = uy - hiy, sl = loy - uy;
+          if (su > best) { best = su; bid = 256 + 4 * i + 2; }
+          else if (sl > best) { best = sl; bid = 256 + 4 * i + 3; }
+        }
+      }
+      static_for<1, KH + 1>([&](auto kc) {
+        constexpr int K = decltype(kc)::value;
+        const T uxj = grot<G, K>(ux, lane), uyj = grot<G, K>(uy, lane);
+        if (cpid[K - 1] >= 0 && !((own_act >> K) & 1u)) {
+          const bool ia = i < ((i + K) & (G - 1));
+          const T dux = ia ? uxj - ux : ux - uxj;
+          const T duy = ia ? uyj - uy : uy - uyj;
+          const T sn = (T(2) * (cdx[K - 1] * dux + cdy[K - 1] * duy) - cb[K - 1]) * crn[K - 1];
+          if (sn > best) {
+            best = sn;
+            bid = cpid[K - 1];
+            bdx = cdx[K - 1];
+            bdy = cdy[K - 1];
+            bbb = cb[K - 1];
+          }
+        }
+      });
+      gargmax_payload<G>(best, bid, bdx, bdy, bbb);
+      if (bid < 0) break;  // optimal
+      if (++info.iters > cap) { info.status = 2; break; }
+      p_pair = bid < 256;
+      pa = p_pair ? (bid >> 4) : ((bid - 256) >> 2);
+      pb = p_pair ? (bid & 15) : -1;
+      pk = p_pair ? 0 : (((bid - 256) >> 1) & 1);
+      psig = p_pair ? 0 : (((bid - 256) & 1) ? -1 : 1);
+      // entering row's coefficients at my robot
+      const T sgn = i == pa ? T(-2) : (i == pb ? T(2) : T(0));
+      cpx = p_pair ? sgn * bdx : ((i == pa && pk == 0) ? T(psig) : T(0));
+      cpy = p_pair ? sgn * bdy : ((i == pa && pk == 1) ? T(psig) : T(0));
+      if (!on) cpx = cpy = T(0);
+      bp = bbb;
+      lam_p = T(0);
+      pend = true;
+    }
+    const bool frx = fx == 0, fry = fy == 0;
+    if (!lvalid) {
+      // refactor the Gram system over the current free coordinates
+      bool pd = true;
+#pragma unroll
+      for (int a = 0; a < kQR; ++a) {
+#pragma unroll
+        for (int b = 0; b <= a; ++b) {
+          T sgm = gsum<G>((frx ? ccx[a] * ccx[b] : T(0)) + (fry ? ccy[a] * ccy[b] : T(0)));
+#pragma unroll
+          for (int k2 = 0; k2 < b; ++k2) sgm -= L[tri(a, k2)] * L[tri(b, k2)];
+          if (b == a) {
+            sgm = a < q ? sgm : T(1);
+            pd = pd && (sgm > T(0));
+            const T rs = rsqrt_t(tmax(sgm, T(1e-30)));
+            L[tri(a, a)] = sgm * rs;
+            Linv[a] = rs;
+          } else {
+            L[tri(a, b)] = sgm * Linv[b];
+          }
+        }
+      }
+      if (!pd) { restart = true; break; }
+      lvalid = true;
+    }
+    // g = C_S^free c_p, w = L^-1 g, r = L^-T w (zero on unused slots)
+    T w[kQR], rv[kQR];
+#pragma unroll
+    for (int a = 0; a < kQR; ++a) {
+      T g = gsum<G>((frx ? ccx[a] * cpx : T(0)) + (fry ? ccy[a] * cpy : T(0)));
+#pragma unroll
+      for (int k2 = 0; k2 < a; ++k2) g -= L[tri(a, k2)] * w[k2];
+      w[a] = g * Linv[a];
+    }
+#pragma unroll
+    for (int a = kQR - 1; a >= 0; --a) {
+      T sgm = w[a];
+#pragma unroll
+      for (int k2 = a + 1; k2 < kQR; ++k2) sgm -= L[tri(k2, a)] * rv[k2];
+      rv[a] = sgm * Linv[a];
+    }
+    // C_S^T r at my robot, the primal direction z (free coordinates) and the
+    // direction of my fixed bounds' multipliers
+    T crx = T(0), cry = T(0);
+#pragma unroll
+    for (int a = 0; a < kQR; ++a) {
+      crx += rv[a] * ccx[a];
+      cry += rv[a] * ccy[a];
+    }
+    const T zx = frx ? cpx - crx : T(0);
+    const T zy = fry ? cpy - cry : T(0);
+    const T rfx = frx ? T(0) : T(fx) * (cpx - crx);
+    const T rfy = fry ? T(0) : T(fy) * (cpy - cry);
+    const T zz = gsum<G>(zx * zx + zy * zy);
+    const T cpn2 = gsum<G>((frx ? cpx * cpx : T(0)) + (fry ? cpy * cpy : T(0)));
+    // blocking step t1 over active rows (uniform) and my fixed bounds
+    T t1 = BIG;
+    int drop = -1;
+#pragma unroll
+    for (int a = 0; a < kQR; ++a) {
+      const T ratio = qdiv(slam[a], rv[a]);
+      const bool ok = a < q && rv[a] > C.eps_r && ratio < t1;
+      t1 = ok ? ratio : t1;
+      drop = ok ? a : drop;
+    }
+    {
+      const T rx = qdiv(mux, rfx), ry = qdiv(muy, rfy);
+      const bool okx = on && !frx && rfx > C.eps_r && (rx < t1 || (rx == t1 && drop < 0));
+      t1 = okx ? rx : t1;
+      drop = okx ? 1024 + 2 * i : drop;
+      const bool oky = on && !fry && rfy > C.eps_r && (ry < t1 || (ry == t1 && drop < 0));
+      t1 = oky ? ry : t1;
+      drop = oky ? 1024 + 2 * i + 1 : drop;
+    }
+    gargmin<G>(t1, drop);
+    // current violation of p
+    T contrib = p_pair ? cpx * ux + cpy * uy : T(0);
+    if (!p_pair && on && i == pa)
+      contrib = pk ? (psig > 0 ? uy - hiy : loy - uy) : (psig > 0 ? ux - hix : lox - ux);
+    const T sp = gsum<G>(contrib) - (p_pair ? bp : T(0));
+    const bool z_ok = zz > C.eps_z * cpn2;
+    const T t2 = z_ok ? qdiv(sp, zz) : BIG;
+    if (drop < 0 && !z_ok) { dead = true; break; }
+    const bool full = z_ok && (drop < 0 || t2 <= t1);
+    const T t = full ? t2 : t1;
+    if (full && p_pair && q == kQR) { restart = true; break; }  // no slot left
+    const T tz = z_ok ? t : T(0);
+    ux -= tz * zx;
+    uy -= tz * zy;
+#pragma unroll
+    for (int a = 0; a < kQR; ++a) slam[a] -= a < q ? t * rv[a] : T(0);
+    mux -= t * rfx;
+    muy -= t * rfy;
+    lam_p += t;
+    if (full && p_pair) {
+      // append p at slot q and extend the factor: L[q] = [w, |z|]
+      const T rz = rsqrt_t(zz);
+#pragma unroll
+      for (int a = 0; a < kQR; ++a) {
+        const bool here = a == q;
+        sa[a] = here ? pa : sa[a];
+        sb[a] = here ? pb : sb[a];
+        slam[a] = here ? lam_p : slam[a];
+        ccx[a] = here ? cpx : ccx[a];
+        ccy[a] = here ? cpy : ccy[a];
+#pragma unroll
+        for (int k2 = 0; k2 < a; ++k2) L[tri(a, k2)] = here ? w[k2] : L[tri(a, k2)];
+        L[tri(a, a)] = here ? zz * rz : L[tri(a, a)];
+        Linv[a] = here ? rz : Linv[a];
+      }
+      ++q;
+      int owner, kk;
+      pair_owner_g<G>(pa, pb, owner, kk);
+      if (i == owner) own_act |= 1u << kk;
+    } else if (full) {
+      // p is a bound: fix the coordinate
+      if (i == pa) {
+        if (pk) { fy = psig; muy = lam_p; uy = psig > 0 ? hiy : loy; }
+        else { fx = psig; mux = lam_p; ux = psig > 0 ? hix : lox; }
+      }
+      lvalid = false;
+    } else if (drop >= 1024) {
+      const int r = (drop - 1024) >> 1, cc2 = (drop - 1024) & 1;
+      if (i == r) {
+        if (cc2) { fy = 0; muy = T(0); } else { fx = 0; mux = T(0); }
+      }
+      lvalid = false;
+    } else {
+      // release active row `drop`: shift the later slots down
+      int owner = 0, kk = 0;
+#pragma unroll
+      for (int a = 0; a < kQR; ++a)
+        if (a == drop) pair_owner_g<G>(sa[a], sb[a], owner, kk);
+      if (i == owner) own_act &= ~(1u << kk);
+#pragma unroll
+      for (int a = 0; a < kQR; ++a) {
+        const bool mv = a >= drop && a + 1 < q;
+        const bool clr = a >= drop && !mv;
+        if (a + 1 < kQR) {
+          sa[a] = mv ? sa[a + 1] : (clr ? -1 : sa[a]);
+          sb[a] = mv ? sb[a + 1] : (clr ? -1 : sb[a]);
+          slam[a] = mv ? slam[a + 1] : (clr ? T(0) : slam[a]);
+          ccx[a] = mv ? ccx[a + 1] : (clr ? T(0) : ccx[a]);
+          ccy[a] = mv ? ccy[a + 1] : (clr ? T(0) : ccy[a]);
+        } else if (clr) {
+          sa[a] = sb[a] = -1;
+          slam[a] = ccx[a] = ccy[a] = T(0);
+        }
+      }
+      --q;
+      lvalid = false;
+    }
+    if (full) pend = false;
+    if (++info.iters > cap) { info.status = 2; break; }
   }
 
   if (restart && !dead) {
