@@ -199,4 +199,22 @@ template <typename T> struct SimConst {
   double grid;
 };
 
+// Reference to the launch's SimConst in the kernel-argument segment. A field
+// read through it is loaded (by a scalar load) where it is used, so constants
+// needed only on cold paths (reset sampler, stream key) do not hold scalar
+// registers across a step loop.
+template <typename T> struct ConstRef {
+  uint64_t addr;
+  __device__ __forceinline__ const __attribute__((address_space(4))) SimConst<T> *get() const {
+    uint64_t a = addr;
+    asm volatile("" : "+s"(a));  // opaque: the load stays at the use
+    return (const __attribute__((address_space(4))) SimConst<T> *)a;
+  }
+};
+// `offset` = offsetof(kernel argument struct, its SimConst member); the
+// struct must be the kernel's first parameter.
+template <typename T> __device__ __forceinline__ ConstRef<T> kernarg_const(size_t offset) {
+  return ConstRef<T>{(uint64_t)__builtin_amdgcn_kernarg_segment_ptr() + offset};
+}
+
 }  // namespace rs

@@ -8,6 +8,8 @@
 // consecutive elements: the loads coalesce. The QP scratch of each group
 // lives in LDS.
 #include "rs_internal.hpp"
+
+#include <cstddef>
 #include "rs_step.hpp"
 
 #include <cstring>
@@ -80,12 +82,14 @@ __global__ __launch_bounds__(kBlock) void k_env_step(StepArgs<T> A) {
   T x = A.x[r], y = A.y[r], th = A.th[r], gx = A.gx[r], gy = A.gy[r];
   int step = A.step[e], episode = A.episode[e];
   const uint32_t env_id = A.env_base + (uint32_t)e;
+  const ConstRef<T> K = kernarg_const<T>(offsetof(StepArgs<T>, C));
   int action = 0;
   if (A.C.controller == 0)
-    action = A.actions ? (int)A.actions[r] : drawn_action(A.C.key0, A.C.key1, env_id, A.t_global, i);
+    action = A.actions ? (int)A.actions[r]
+                       : drawn_action(K.get()->key0, K.get()->key1, env_id, A.t_global, i);
   T s, c;
   sincos_t(th, &s, &c);
-  StepOut<T> out = env_step_group<T, G>(A.C, &qs[threadIdx.x / G], lane, i, N, on, env_id, action,
+  StepOut<T> out = env_step_group<T, G>(A.C, K, &qs[threadIdx.x / G], lane, i, N, on, env_id, action,
                                         x, y, th, c, s, gx, gy, step, episode,
                                         A.maxviol != nullptr);
   if (on) {
@@ -127,7 +131,8 @@ __global__ __launch_bounds__(kBlock) void k_env_reset(ResetArgs<T> A) {
   const size_t r = (size_t)e * N + (on ? i : 0);
   const int episode = A.episode[e];
   T x, y, th, gx, gy;
-  reset_env<T, G>(A.C, A.env_base + (uint32_t)e, (uint32_t)episode, i, N, lane, x, y, th, gx, gy);
+  reset_env<T, G>(kernarg_const<T>(offsetof(ResetArgs<T>, C)), A.env_base + (uint32_t)e,
+                  (uint32_t)episode, i, N, lane, x, y, th, gx, gy);
   if (on) {
     A.x[r] = x; A.y[r] = y; A.th[r] = th; A.gx[r] = gx; A.gy[r] = gy;
   }

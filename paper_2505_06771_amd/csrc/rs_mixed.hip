@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstddef>
 #include <cstring>
 #include <numeric>
 
@@ -37,11 +38,12 @@ __device__ void run_tile(const RunArgs &A, char *wave_lds, int lane, int first, 
   const uint32_t env_id = A.env_ids ? A.env_ids[e] : A.env_base + (uint32_t)e;
   SimConst<float> C = A.C;
   C.qp_cap = A.qp_iters[N];
+  const ConstRef<float> K = kernarg_const<float>(offsetof(RunArgs, C));
 
   float x = 0.f, y = 0.f, th = 0.f, gx = 0.f, gy = 0.f;
   int step = A.step[e], episode = A.episode[e];
   if (A.reset_mask && A.reset_mask[e]) {
-    reset_env<float, G>(C, env_id, (uint32_t)episode, i, N, lane, x, y, th, gx, gy);
+    reset_env<float, G>(K, env_id, (uint32_t)episode, i, N, lane, x, y, th, gx, gy);
     step = 0;
     if (i == 0) A.reset_mask[e] = 0;
   } else if (on) {
@@ -57,8 +59,9 @@ __device__ void run_tile(const RunArgs &A, char *wave_lds, int lane, int first, 
   sincos_t(th, &s, &c);
   float rsum = 0.f;
   for (int k = 0; k < nsteps; ++k) {
-    const int action = drawn_action(C.key0, C.key1, env_id, (uint32_t)(tb + k), i);
-    const StepOut<float> so = env_step_group<float, G>(C, sh, lane, i, N, on, env_id, action, x, y,
+    const auto *P = K.get();
+    const int action = drawn_action(P->key0, P->key1, env_id, (uint32_t)(tb + k), i);
+    const StepOut<float> so = env_step_group<float, G>(C, K, sh, lane, i, N, on, env_id, action, x, y,
                                                        th, c, s, gx, gy, step, episode, false);
     rsum += so.reward;
     if (i == 0) {

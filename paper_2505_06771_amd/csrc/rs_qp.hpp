@@ -438,6 +438,19 @@ __device__ __forceinline__ void gargmax_payload(T &v, int &id, T &p0, T &p1, T &
   if constexpr (G >= 16) step(std::integral_constant<int, 0x140>{});
 }
 
+template <int G, typename T> __device__ __forceinline__ void gargmax(T &v, int &id) {
+  auto step = [&](auto cc) {
+    constexpr int CT = decltype(cc)::value;
+    const T w = dpp<CT>(v);
+    const int j = dpp<CT>(id);
+    if (w > v || (w == v && j < id)) { v = w; id = j; }
+  };
+  step(std::integral_constant<int, 0xB1>{});
+  if constexpr (G >= 4) step(std::integral_constant<int, 0x4E>{});
+  if constexpr (G >= 8) step(std::integral_constant<int, 0x141>{});
+  if constexpr (G >= 16) step(std::integral_constant<int, 0x140>{});
+}
+
 template <int G, typename T> __device__ __forceinline__ void gargmin(T &v, int &id) {
   auto step = [&](auto cc) {
     constexpr int CT = decltype(cc)::value;
@@ -458,14 +471,40 @@ template <int G> __device__ __forceinline__ void pair_owner_g(int a, int b, int 
   else { owner = b; k = G - d; }
 }
 
+// Result of the active-set loop (commands, status and the active rows).
+template <typename T> struct QPLoopOut {
+  T ux, uy;
+  int status, iters, q, in_lds;
+  int sa[kQR], sb[kQR];
+  T slam[kQR];
+};
+
+// The active-set loop, kept out of line: it runs for the few environments the
+// closed-form stages leave, and inlined its registers would weigh on every
+// step. It rebuilds the pair geometry and the box clip from the arguments and
+// starts from the box clip or, with `seed`, from the one-row solution of row
+// (fpa, fpb) with multiplier fl1 (fdx, fdy = p_a - p_b). Every lane of the
+// group calls it together. Only scalars cross the call.
 template <typename T, int G>
-__device__ QPInfo qp_solve(QPScratch<T, G> *sh, const SimConst<T> &C, int lane, int i, int N,
-                           bool on, T px, T py, T uhx, T uhy, T lox, T hix, T loy, T hiy, T &ux,
-                           T &uy, QPActive<T> *act_out = nullptr) {
+__device__ __noinline__ QPLoopOut<T> qp_active_set(QPScratch<T, G> *sh, int lane, int i, int N,
+                                                   bool on, T px, T py, T uhx, T uhy, T lox,
+                                                   T hix, T loy, T hiy, bool seed, int fpa,
+                                                   int fpb, T fl1, T fdx, T fdy, T rs2, T gamma,
+                                                   T vmax4, T tol_add, T eps_z, T eps_r,
+                                                   int qp_cap) {
   constexpr int KH = G / 2;
   const T BIG = big_v<T>();
+  SimConst<T> C{};
+  C.rs2 = rs2;
+  C.gamma = gamma;
+  C.vmax4 = vmax4;
+  C.tol_add = tol_add;
+  C.eps_z = eps_z;
+  C.eps_r = eps_r;
+  C.qp_cap = qp_cap;
   QPInfo info{0, 0, 0, 0};
-
+  bool dead = false;
+  T ux, uy;
   // --- geometry of the owned pairs ------------------------------------------
   T cdx[KH], cdy[KH], cb[KH], crn[KH];
   int cpid[KH];
@@ -489,8 +528,6 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, const SimConst<T> &C, int lane, 
     cpid[K - 1] = (cand && d2 > T(0)) ? ((ia ? i : j) << 4 | (ia ? j : i)) : -1;
     if (cand && !(d2 > T(0)) && bb < T(0)) coincide = true;
   });
-  bool dead = group_any<G>(coincide || (on && (lox > hix || loy > hiy)), lane);
-
   // --- start: clip to the box; active bounds fix their coordinate ----------
   int fx = 0, fy = 0;
   T mux = T(0), muy = T(0);
@@ -503,6 +540,7 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, const SimConst<T> &C, int lane, 
     else if (uhy < loy) { uy = loy; fy = -1; muy = loy - uhy; }
   }
 
+  const int cap = C.qp_cap > 0 ? C.qp_cap : 8 * N + 32;
   // Active pairwise rows: group-uniform slots (robots, multiplier) and, per
   // lane, the row's coefficients at the lane's robot (zero unless the robot is
   // one of the row's two ends). Gram entries and the products with the
@@ -525,136 +563,35 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, const SimConst<T> &C, int lane, 
     for (int b = 0; b <= a; ++b) L[tri(a, b)] = T(0);
   }
   uint32_t own_act = 0;
-  const int cap = C.qp_cap > 0 ? C.qp_cap : 8 * N + 32;
   bool restart = false;
 
-  // --- one-row fast path -----------------------------------------------------
-  // Every bound holds at the box clip. When exactly one pairwise row p (robots
-  // a < b) is violated there, the projection onto box & {c_p.u <= b_p} has a
-  // closed form: u(l) = clip(u_nom - l c_p), where l >= 0 is the root of the
-  // non-increasing, piecewise linear phi(l) = c_p.u(l) - b_p, whose breakpoints
-  // are where a coordinate of robot a or b meets a bound. Only robots a and b
-  // move, so when every row through a or b holds at u(l), u(l) satisfies the
-  // whole problem; as the minimiser over a superset of its feasible set it is
-  // the solution. Otherwise u(l), with p active and the clipped coordinates
-  // fixed, is a dual-feasible start for the active-set loop below.
-  bool run_gi = !dead;
-  if (!dead) {
-    T best = C.tol_add, bdx = T(0), bdy = T(0), bbb = T(0);
-    int bid = -1, nviol = 0;
-    static_for<1, KH + 1>([&](auto kc) {
-      constexpr int K = decltype(kc)::value;
-      const T uxj = grot<G, K>(ux, lane), uyj = grot<G, K>(uy, lane);
-      if (cpid[K - 1] >= 0) {
-        const bool ia = i < ((i + K) & (G - 1));
-        const T dux = ia ? uxj - ux : ux - uxj;
-        const T duy = ia ? uyj - uy : uy - uyj;
-        const T sn = (T(2) * (cdx[K - 1] * dux + cdy[K - 1] * duy) - cb[K - 1]) * crn[K - 1];
-        nviol += sn > C.tol_add ? 1 : 0;
-        if (sn > best) {
-          best = sn;
-          bid = cpid[K - 1];
-          bdx = cdx[K - 1];
-          bdy = cdy[K - 1];
-          bbb = cb[K - 1];
-        }
-      }
-    });
-    gargmax_payload<G>(best, bid, bdx, bdy, bbb);
-    const int nv = gsum<G>(nviol);
-    if (bid < 0) {
-      run_gi = false;  // the box clip is the solution
-    } else if (nv == 1) {
-      const int gbase = lane & ~(G - 1);
-      const int pa = bid >> 4, pb = bid & 15;
-      const int la = gbase + pa, lb = gbase + pb;
-      // coordinates 0..3 = (a.x, a.y, b.x, b.y) and their row coefficients
-      const T cc[4] = {T(-2) * bdx, T(-2) * bdy, T(2) * bdx, T(2) * bdy};
-      const T un[4] = {__shfl(uhx, la, 64), __shfl(uhy, la, 64), __shfl(uhx, lb, 64),
-                       __shfl(uhy, lb, 64)};
-      const T lo[4] = {__shfl(lox, la, 64), __shfl(loy, la, 64), __shfl(lox, lb, 64),
-                       __shfl(loy, lb, 64)};
-      const T hi[4] = {__shfl(hix, la, 64), __shfl(hiy, la, 64), __shfl(hix, lb, 64),
-                       __shfl(hiy, lb, 64)};
-      T e1[4], e2[4];  // multiplier values where coordinate k meets hi_k / lo_k
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const T r = cc[k] != T(0) ? qdiv(T(1), cc[k]) : T(0);
-        e1[k] = (un[k] - hi[k]) * r;
-        e2[k] = (un[k] - lo[k]) * r;
-      }
-      auto phi = [&](T lm) {
-        T acc = -bbb;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) acc += cc[k] * tclamp(un[k] - lm * cc[k], lo[k], hi[k]);
-        return acc;
-      };
-      // largest breakpoint (or 0) where phi is still positive
-      T llo = T(0), plo = phi(T(0));
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const T p1 = phi(e1[k]), p2 = phi(e2[k]);
-        if (p1 > T(0) && e1[k] > llo) { llo = e1[k]; plo = p1; }
-        if (p2 > T(0) && e2[k] > llo) { llo = e2[k]; plo = p2; }
-      }
-      // slope of -phi just right of llo: coordinates still free there
-      T slope = T(0);
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const bool fr = cc[k] != T(0) && tmin(e1[k], e2[k]) <= llo && llo < tmax(e1[k], e2[k]);
-        slope += fr ? cc[k] * cc[k] : T(0);
-      }
-      if (slope > T(0)) {
-        const T lam = tmax(llo + qdiv(plo, slope), T(0));
-        T uu[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) uu[k] = tclamp(un[k] - lam * cc[k], lo[k], hi[k]);
-        // rows through a or b, in the scan's normalised form
-        const T pxa = __shfl(px, la, 64), pya = __shfl(py, la, 64);
-        const T pxb = __shfl(px, lb, 64), pyb = __shfl(py, lb, 64);
-        bool bad = false;
-        if (on && i != pa && i != pb) {
-          auto row_viol = [&](T pxr, T pyr, T uxr, T uyr) {
-            const T dx = pxr - px, dy = pyr - py;
-            const T d2 = dx * dx + dy * dy;
-            const T h = d2 - C.rs2;
-            const T sn = T(2) * (dx * (ux - uxr) + dy * (uy - uyr)) - C.gamma * (h * h * h);
-            return d2 > T(0) ? sn * (T(0.35355339059327373) * rsqrt_t(d2)) : sn;
-          };
-          bad = row_viol(pxa, pya, uu[0], uu[1]) > C.tol_add ||
-                row_viol(pxb, pyb, uu[2], uu[3]) > C.tol_add;
-        }
-        // adopt u(l) with p active; the loop continues from it if needed
-        run_gi = group_any<G>(bad, lane);
-        info.iters = 1;
-        q = 1;
-        sa[0] = pa;
-        sb[0] = pb;
-        slam[0] = lam;
-        lvalid = false;
-        {
-          int owner, kk;
-          pair_owner_g<G>(pa, pb, owner, kk);
-          if (i == owner) own_act |= 1u << kk;
-        }
-        const bool ma = i == pa, mb = i == pb;
-        ccx[0] = ma ? cc[0] : (mb ? cc[2] : T(0));
-        ccy[0] = ma ? cc[1] : (mb ? cc[3] : T(0));
-        if (ma || mb) {
-          // free or clipped at the multiplier lam: fixed coordinates carry
-          // the bound multiplier that makes the point stationary
-          const T vx = (ma ? un[0] : un[2]) - lam * ccx[0];
-          const T vy = (ma ? un[1] : un[3]) - lam * ccy[0];
-          ux = ma ? uu[0] : uu[2];
-          uy = ma ? uu[1] : uu[3];
-          fx = vx > hix ? 1 : (vx < lox ? -1 : 0);
-          mux = vx > hix ? vx - hix : (vx < lox ? lox - vx : T(0));
-          fy = vy > hiy ? 1 : (vy < loy ? -1 : 0);
-          muy = vy > hiy ? vy - hiy : (vy < loy ? loy - vy : T(0));
-        }
-      }
+  if (seed) {
+    // row (fpa, fpb) active with multiplier fl1; its robots' coordinates are
+    // free or clipped at that multiplier, and the clipped ones are fixed with
+    // the bound multiplier that makes the point stationary
+    q = 1;
+    sa[0] = fpa;
+    sb[0] = fpb;
+    slam[0] = fl1;
+    lvalid = false;
+    info.iters = 1;
+    int owner, kk;
+    pair_owner_g<G>(fpa, fpb, owner, kk);
+    if (i == owner) own_act |= 1u << kk;
+    ccx[0] = i == fpa ? T(-2) * fdx : (i == fpb ? T(2) * fdx : T(0));
+    ccy[0] = i == fpa ? T(-2) * fdy : (i == fpb ? T(2) * fdy : T(0));
+    if (on && (i == fpa || i == fpb)) {
+      const T vx = uhx - fl1 * ccx[0];
+      const T vy = uhy - fl1 * ccy[0];
+      ux = tclamp(vx, lox, hix);
+      uy = tclamp(vy, loy, hiy);
+      fx = vx > hix ? 1 : (vx < lox ? -1 : 0);
+      mux = vx > hix ? vx - hix : (vx < lox ? lox - vx : T(0));
+      fy = vy > hiy ? 1 : (vy < loy ? -1 : 0);
+      muy = vy > hiy ? vy - hiy : (vy < loy ? loy - vy : T(0));
     }
   }
+  const bool run_gi = true;
 
   // --- active-set loop ---------------------------------------------------------
   // One flat loop. Without a pending row an iteration picks the most violated
@@ -881,27 +818,340 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, const SimConst<T> &C, int lane, 
     if (++info.iters > cap) { info.status = 2; break; }
   }
 
+  QPLoopOut<T> out;
   if (restart && !dead) {
     // more active rows than register slots (or a degenerate Gram system):
     // solve again with the general solver
-    return qp_solve_lds<T, G>(sh, C, lane, i, N, on, px, py, uhx, uhy, lox, hix, loy, hiy, ux, uy);
+    const QPInfo r = qp_solve_lds<T, G>(sh, C, lane, i, N, on, px, py, uhx, uhy, lox, hix, loy,
+                                        hiy, ux, uy);
+    info.status = r.status;
+    info.iters += r.iters;
+    q = r.q;
+    out.in_lds = 1;
+  } else {
+    out.in_lds = 0;
+    if (dead) {
+      info.status = 1;
+      q = 0;
+      if (on) {
+        ux = lox <= hix ? tmin(tmax(uhx, lox), hix) : T(0.5) * (lox + hix);
+        uy = loy <= hiy ? tmin(tmax(uhy, loy), hiy) : T(0.5) * (loy + hiy);
+      }
+    }
+  }
+  out.ux = ux;
+  out.uy = uy;
+  out.status = info.status;
+  out.iters = info.iters;
+  out.q = q;
+#pragma unroll
+  for (int a = 0; a < kQR; ++a) {
+    out.sa[a] = sa[a];
+    out.sb[a] = sb[a];
+    out.slam[a] = slam[a];
+  }
+  return out;
+}
+
+template <typename T, int G>
+__device__ QPInfo qp_solve(QPScratch<T, G> *sh, const SimConst<T> &C, int lane, int i, int N,
+                           bool on, T px, T py, T uhx, T uhy, T lox, T hix, T loy, T hiy, T &ux,
+                           T &uy, QPActive<T> *act_out = nullptr) {
+  constexpr int KH = G / 2;
+  const T BIG = big_v<T>();
+  QPInfo info{0, 0, 0, 0};
+
+  // --- geometry of the owned pairs ------------------------------------------
+  T cdx[KH], cdy[KH], cb[KH], crn[KH];
+  int cpid[KH];
+  bool coincide = false;
+  static_for<1, KH + 1>([&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    const T pxj = grot<G, K>(px, lane), pyj = grot<G, K>(py, lane);
+    const int j = (i + K) & (G - 1);
+    const bool valid = on && j < N && !(2 * K == G && i >= KH);
+    const bool ia = i < j;
+    const T dx = ia ? px - pxj : pxj - px;
+    const T dy = ia ? py - pyj : pyj - py;
+    const T d2 = dx * dx + dy * dy;
+    const T h = d2 - C.rs2;
+    const T bb = C.gamma * (h * h * h);
+    const bool cand = valid && (C.vmax4 * (tabs(dx) + tabs(dy)) > bb);
+    cdx[K - 1] = dx;
+    cdy[K - 1] = dy;
+    cb[K - 1] = bb;
+    crn[K - 1] = d2 > T(0) ? T(0.35355339059327373) * rsqrt_t(d2) : T(0);
+    cpid[K - 1] = (cand && d2 > T(0)) ? ((ia ? i : j) << 4 | (ia ? j : i)) : -1;
+    if (cand && !(d2 > T(0)) && bb < T(0)) coincide = true;
+  });
+  bool dead = group_any<G>(coincide || (on && (lox > hix || loy > hiy)), lane);
+
+  // --- start: clip to the box; active bounds fix their coordinate ----------
+  int fx = 0, fy = 0;
+  T mux = T(0), muy = T(0);
+  ux = uhx;
+  uy = uhy;
+  if (on) {
+    if (uhx > hix) { ux = hix; fx = 1; mux = uhx - hix; }
+    else if (uhx < lox) { ux = lox; fx = -1; mux = lox - uhx; }
+    if (uhy > hiy) { uy = hiy; fy = 1; muy = uhy - hiy; }
+    else if (uhy < loy) { uy = loy; fy = -1; muy = loy - uhy; }
+  }
+
+  const int cap = C.qp_cap > 0 ? C.qp_cap : 8 * N + 32;
+  // outcome of the closed-form stages: rows accepted (fq = 1 or 2), or a
+  // one-row start for the active-set loop (seed)
+  int fq = 0, fpa = -1, fpb = -1, fqa = -1, fqb = -1;
+  T fl1 = T(0), fl2 = T(0), fdx = T(0), fdy = T(0);
+  bool seed = false;
+
+  // --- closed-form stages --------------------------------------------------------
+  // Every bound holds at the box clip u0. If at most two pairwise rows are
+  // violated there, the solution is guessed in closed form and accepted when it
+  // satisfies every row through the robots it moves (rows away from them keep
+  // their values at u0, where only the guessed rows were violated): being the
+  // minimiser over a superset of the feasible set, a feasible guess is the
+  // solution.
+  //  * One row p = (a, b), or two rows on four distinct robots: each row's
+  //    projection onto box & {c.u <= b} is u(l) = clip(u_nom - l c), with
+  //    l >= 0 the root of the non-increasing, piecewise linear
+  //    phi(l) = c.u(l) - b; its breakpoints are where a coordinate of the
+  //    row's two robots meets a bound.
+  //  * Two rows through a shared robot: assuming no bound binds on the three
+  //    robots, the multipliers solve the 2 x 2 Gram system; the guess also
+  //    needs both multipliers >= 0 and the three commands inside their bounds.
+  // A rejected one-row guess (with p active and the clipped coordinates fixed)
+  // is a dual-feasible start for the active-set loop below; otherwise the loop
+  // starts from u0.
+  bool run_gi = !dead;
+  if (!dead) {
+    T best = C.tol_add, bdx = T(0), bdy = T(0), bbb = T(0);
+    int bid = -1, nviol = 0;
+    T snk[KH];
+    static_for<1, KH + 1>([&](auto kc) {
+      constexpr int K = decltype(kc)::value;
+      const T uxj = grot<G, K>(ux, lane), uyj = grot<G, K>(uy, lane);
+      const bool ia = i < ((i + K) & (G - 1));
+      const T dux = ia ? uxj - ux : ux - uxj;
+      const T duy = ia ? uyj - uy : uy - uyj;
+      const T sn = (T(2) * (cdx[K - 1] * dux + cdy[K - 1] * duy) - cb[K - 1]) * crn[K - 1];
+      snk[K - 1] = cpid[K - 1] >= 0 ? sn : -BIG;
+      nviol += snk[K - 1] > C.tol_add ? 1 : 0;
+      if (snk[K - 1] > best) {
+        best = sn;
+        bid = cpid[K - 1];
+        bdx = cdx[K - 1];
+        bdy = cdy[K - 1];
+        bbb = cb[K - 1];
+      }
+    });
+    gargmax_payload<G>(best, bid, bdx, bdy, bbb);
+    const int nv = gsum<G>(nviol);
+    if (bid < 0) {
+      run_gi = false;  // u0 is the solution
+    } else if (nv <= 2) {
+      const int gbase = lane & ~(G - 1);
+      // the other violated row, if any
+      T b2 = C.tol_add, e2x = T(0), e2y = T(0), beta2 = T(0);
+      int id2 = -1;
+      if (nv == 2) {
+        static_for<1, KH + 1>([&](auto kc) {
+          constexpr int K = decltype(kc)::value;
+          if (cpid[K - 1] != bid && snk[K - 1] > b2) {
+            b2 = snk[K - 1];
+            id2 = cpid[K - 1];
+            e2x = cdx[K - 1];
+            e2y = cdy[K - 1];
+            beta2 = cb[K - 1];
+          }
+        });
+        gargmax_payload<G>(b2, id2, e2x, e2y, beta2);
+      }
+      const bool two = nv == 2 && id2 >= 0;
+      const int pa = bid >> 4, pb = bid & 15;
+      const int qa = two ? id2 >> 4 : pa, qb = two ? id2 & 15 : pb;
+      const bool disjoint = qa != pa && qa != pb && qb != pa && qb != pb;
+      bool ok = true;
+      T lam1 = T(0), lam2 = T(0);
+      if (!two || disjoint) {
+        // projection onto box & one half-space for each row, on its own two
+        // robots; rows one after the other (a true loop keeps the registers
+        // of one row), each committing its robots' commands in their lanes
+#pragma unroll 1
+        for (int rr = 0; rr < (two ? 2 : 1); ++rr) {
+          const bool r2 = rr == 1;
+          const int ra = r2 ? qa : pa, rb = r2 ? qb : pb;
+          const T dx = r2 ? e2x : bdx, dy = r2 ? e2y : bdy;
+          const T beta = r2 ? beta2 : bbb;
+          const int la = gbase + ra, lb = gbase + rb;
+          const T cc[4] = {T(-2) * dx, T(-2) * dy, T(2) * dx, T(2) * dy};
+          const T un[4] = {__shfl(uhx, la, 64), __shfl(uhy, la, 64), __shfl(uhx, lb, 64),
+                           __shfl(uhy, lb, 64)};
+          T lo[4], hi[4];
+          wall_bounds(C, __shfl(px, la, 64), __shfl(py, la, 64), lo[0], hi[0], lo[1], hi[1]);
+          wall_bounds(C, __shfl(px, lb, 64), __shfl(py, lb, 64), lo[2], hi[2], lo[3], hi[3]);
+          T e1[4], e2[4];  // multiplier values where coordinate k meets hi_k / lo_k
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const T r = cc[k] != T(0) ? qdiv(T(1), cc[k]) : T(0);
+            e1[k] = (un[k] - hi[k]) * r;
+            e2[k] = (un[k] - lo[k]) * r;
+          }
+          auto phi = [&](T lm) {
+            T acc = -beta;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc += cc[k] * tclamp(un[k] - lm * cc[k], lo[k], hi[k]);
+            return acc;
+          };
+          // largest breakpoint (or 0) where phi is still positive
+          T llo = T(0), plo = phi(T(0));
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const T p1 = phi(e1[k]), p2 = phi(e2[k]);
+            if (p1 > T(0) && e1[k] > llo) { llo = e1[k]; plo = p1; }
+            if (p2 > T(0) && e2[k] > llo) { llo = e2[k]; plo = p2; }
+          }
+          // slope of -phi just right of llo: coordinates still free there
+          T slope = T(0);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const bool fr = cc[k] != T(0) && tmin(e1[k], e2[k]) <= llo && llo < tmax(e1[k], e2[k]);
+            slope += fr ? cc[k] * cc[k] : T(0);
+          }
+          ok = ok && slope > T(0);
+          const T lam = tmax(llo + qdiv(plo, tmax(slope, T(1e-30))), T(0));
+          if (i == ra) {
+            ux = tclamp(un[0] - lam * cc[0], lo[0], hi[0]);
+            uy = tclamp(un[1] - lam * cc[1], lo[1], hi[1]);
+          } else if (i == rb) {
+            ux = tclamp(un[2] - lam * cc[2], lo[2], hi[2]);
+            uy = tclamp(un[3] - lam * cc[3], lo[3], hi[3]);
+          }
+          lam2 = r2 ? lam : lam2;
+          lam1 = r2 ? lam1 : lam;
+        }
+      } else {
+        // two rows through a shared robot r; j is p2's other end. With no
+        // bound binding on a, b, j: u = u_nom - lam1 c1 - lam2 c2 there.
+        const int r = (qa == pa || qb == pa) ? pa : pb;
+        const int j = qa == r ? qb : qa;
+        const T c1x = i == pa ? T(-2) * bdx : (i == pb ? T(2) * bdx : T(0));
+        const T c1y = i == pa ? T(-2) * bdy : (i == pb ? T(2) * bdy : T(0));
+        const T c2x = i == qa ? T(-2) * e2x : (i == qb ? T(2) * e2x : T(0));
+        const T c2y = i == qa ? T(-2) * e2y : (i == qb ? T(2) * e2y : T(0));
+        const T g11 = T(8) * (bdx * bdx + bdy * bdy);
+        const T g22 = T(8) * (e2x * e2x + e2y * e2y);
+        const T g12 = gsum<G>(c1x * c2x + c1y * c2y);
+        const T h1 = gsum<G>(c1x * uhx + c1y * uhy) - bbb;
+        const T h2 = gsum<G>(c2x * uhx + c2y * uhy) - beta2;
+        const T det = g11 * g22 - g12 * g12;
+        const T idet = qdiv(T(1), det);
+        lam1 = (g22 * h1 - g12 * h2) * idet;
+        lam2 = (g11 * h2 - g12 * h1) * idet;
+        ok = det > T(1e-6) * g11 * g22 && lam1 >= T(0) && lam2 >= T(0);
+        bool out = false;
+        if (i == pa || i == pb || i == j) {
+          ux = uhx - lam1 * c1x - lam2 * c2x;
+          uy = uhy - lam1 * c1y - lam2 * c2y;
+          out = ux < lox || ux > hix || uy < loy || uy > hiy;
+        }
+        ok = ok && !group_any<G>(out, lane);
+      }
+      // check every row through a moved robot, except the guessed ones
+      const int mr[4] = {pa, pb, qa, qb};
+      bool bad = !ok;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int x = mr[m], lx = gbase + x;
+        const T pxx = __shfl(px, lx, 64), pyx = __shfl(py, lx, 64);
+        const T uxx = __shfl(ux, lx, 64), uyx = __shfl(uy, lx, 64);
+        const bool guessed = (x == pa && i == pb) || (x == pb && i == pa) ||
+                             (two && ((x == qa && i == qb) || (x == qb && i == qa)));
+        if (on && x != i && !guessed) {
+          const T dx = pxx - px, dy = pyx - py;
+          const T d2 = dx * dx + dy * dy;
+          const T h = d2 - C.rs2;
+          T sn = T(2) * (dx * (ux - uxx) + dy * (uy - uyx)) - C.gamma * (h * h * h);
+          sn = d2 > T(0) ? sn * (T(0.35355339059327373) * rsqrt_t(d2)) : sn;
+          bad = bad || sn > C.tol_add;
+        }
+      }
+      const bool accept = !group_any<G>(bad, lane);
+      const bool moved = i == pa || i == pb || i == qa || i == qb;
+      if (accept) {
+        fq = two ? 2 : 1;
+        fpa = pa; fpb = pb; fl1 = lam1;
+        fqa = qa; fqb = qb; fl2 = lam2;
+        run_gi = false;
+        info.iters = two ? 2 : 1;
+      } else if (!two && ok) {
+        // start the loop from u(l) with p active: fixed coordinates carry the
+        // bound multiplier that makes the point stationary
+        seed = true;
+        fpa = pa; fpb = pb; fl1 = lam1; fdx = bdx; fdy = bdy;
+        info.iters = 1;
+        if (moved) {
+          const T cx = i == pa ? T(-2) * bdx : T(2) * bdx;
+          const T cy = i == pa ? T(-2) * bdy : T(2) * bdy;
+          const T vx = uhx - lam1 * cx;
+          const T vy = uhy - lam1 * cy;
+          fx = vx > hix ? 1 : (vx < lox ? -1 : 0);
+          mux = vx > hix ? vx - hix : (vx < lox ? lox - vx : T(0));
+          fy = vy > hiy ? 1 : (vy < loy ? -1 : 0);
+          muy = vy > hiy ? vy - hiy : (vy < loy ? loy - vy : T(0));
+        }
+      } else if (moved && on) {
+        // back to the box clip
+        ux = tclamp(uhx, lox, hix);
+        uy = tclamp(uhy, loy, hiy);
+      }
+    }
+  }
+
+  if (__builtin_expect(run_gi, 0)) {
+    const QPLoopOut<T> r = qp_active_set<T, G>(sh, lane, i, N, on, px, py, uhx, uhy, lox, hix,
+                                               loy, hiy, seed, fpa, fpb, fl1, fdx, fdy, C.rs2,
+                                               C.gamma, C.vmax4, C.tol_add, C.eps_z, C.eps_r,
+                                               C.qp_cap);
+    ux = r.ux;
+    uy = r.uy;
+    info.status = r.status;
+    info.iters = r.iters;
+    info.q = r.q;
+    info.in_lds = r.in_lds;
+    if (act_out) {
+      act_out->q = r.q;
+#pragma unroll
+      for (int a = 0; a < kQR; ++a) {
+        act_out->sa[a] = r.sa[a];
+        act_out->sb[a] = r.sb[a];
+        act_out->slam[a] = r.slam[a];
+      }
+    }
+    return info;
   }
   if (dead) {
     info.status = 1;
-    q = 0;
+    fq = 0;
     if (on) {
       ux = lox <= hix ? tmin(tmax(uhx, lox), hix) : T(0.5) * (lox + hix);
       uy = loy <= hiy ? tmin(tmax(uhy, loy), hiy) : T(0.5) * (loy + hiy);
     }
   }
-  info.q = q;
+  info.q = fq;
   if (act_out) {
-    act_out->q = q;
+    act_out->q = fq;
+    act_out->sa[0] = fq > 0 ? fpa : -1;
+    act_out->sb[0] = fq > 0 ? fpb : -1;
+    act_out->slam[0] = fq > 0 ? fl1 : T(0);
+    act_out->sa[1] = fq > 1 ? fqa : -1;
+    act_out->sb[1] = fq > 1 ? fqb : -1;
+    act_out->slam[1] = fq > 1 ? fl2 : T(0);
 #pragma unroll
-    for (int a = 0; a < kQR; ++a) {
-      act_out->sa[a] = sa[a];
-      act_out->sb[a] = sb[a];
-      act_out->slam[a] = slam[a];
+    for (int a = 2; a < kQR; ++a) {
+      act_out->sa[a] = -1;
+      act_out->sb[a] = -1;
+      act_out->slam[a] = T(0);
     }
   }
   return info;

@@ -21,6 +21,7 @@
 #include "rs_internal.hpp"
 #include "rs_step.hpp"
 
+#include <cstddef>
 #include <cstring>
 
 namespace rs {
@@ -93,11 +94,13 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
   if (e0 >= A.E) return;  // the whole wavefront leaves together
   const int e = e0 + grp;
   const int N = NC ? NC : A.N;
+  const ConstRef<float> K = kernarg_const<float>(offsetof(RolloutArgs, C));
   const int D = 2 * N + 4;
   const bool env_ok = e < A.E;
   const bool on = env_ok && i < N;
   const int nenv = min(EPW, A.E - e0);
-  const size_t r = on ? (size_t)e * N + i : 0;
+  // robot index (E * N < 2^31, checked by the entry point)
+  const uint32_t r = on ? (uint32_t)(e * N + i) : 0u;
 
   float x = 0.f, y = 0.f, th = 0.f, gx = 0.f, gy = 0.f;
   int step = 0, episode = 0;
@@ -170,7 +173,7 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
     if (on) { o[D - 2] = gx - x; o[D - 1] = gy - y; }
     wave_lds_sync();
     if (A.obs) {
-      float *dst = A.obs + ((size_t)t * A.E + e0) * (size_t)(N * D);
+      float *dst = A.obs + ((size_t)t * A.E + e0) * (size_t)(N * D);  // wavefront-uniform
       if (vec4) {
         for (int q = lane; q < (nfl >> 2); q += 64)
           reinterpret_cast<float4 *>(dst)[q] = reinterpret_cast<const float4 *>(obs_w)[q];
@@ -257,7 +260,8 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
     if constexpr (G >= 4) {
       const int ph = t & 3;
       if (ph == 0) {
-        qblk = stream_block(A.C.key0, A.C.key1, env_id, A.t0 + (uint32_t)(t + (i & 3)), kPolicy,
+        const auto *P = K.get();
+        qblk = stream_block(P->key0, P->key1, env_id, A.t0 + (uint32_t)(t + (i & 3)), kPolicy,
                             (uint32_t)(i >> 2), 0u);
       }
       uint4 src;
@@ -269,7 +273,8 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
       }
       rbits = word(src, i & 3);
     } else {
-      rbits = word(stream_block(A.C.key0, A.C.key1, env_id, A.t0 + (uint32_t)t, kPolicy,
+      const auto *P = K.get();
+      rbits = word(stream_block(P->key0, P->key1, env_id, A.t0 + (uint32_t)t, kPolicy,
                                 (uint32_t)(i >> 2), 0u), i & 3);
     }
     const float u = unit24(rbits);
@@ -281,16 +286,18 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
       cdf += ex[k] * inv_tot;
       if (action == 4 && k < 4 && u < cdf) action = k;
     }
-    if (on) A.actions[((size_t)t * A.E + e) * N + i] = (uint8_t)action;
+    // per-step base pointers are uniform; the lane offsets are 32-bit
+    uint8_t *act_t = A.actions + (size_t)t * (size_t)A.E * (size_t)N;
+    if (on) act_t[r] = (uint8_t)action;
 
     // ---- 4. env step --------------------------------------------------------
     if (env_ok) {
-      const StepOut<float> so = env_step_group<float, G>(A.C, sh, lane, i, N, on, env_id, action,
+      const StepOut<float> so = env_step_group<float, G>(A.C, K, sh, lane, i, N, on, env_id, action,
                                                          x, y, th, c, s, gx, gy, step, episode,
                                                          false);
       if (i == 0) {
-        A.reward[(size_t)t * A.E + e] = so.reward;
-        A.done[(size_t)t * A.E + e] = so.done ? 1 : 0;
+        (A.reward + (size_t)t * A.E)[(uint32_t)e] = so.reward;
+        (A.done + (size_t)t * A.E)[(uint32_t)e] = so.done ? 1 : 0;
       }
     }
   }
@@ -331,6 +338,7 @@ extern "C" rs_status rollout(rs_ctx *ctx, const rs_params *p, const rs_batch *b,
   RS_CHECK_ARG(p->dtype == RS_F32, "rollout runs in FP32 (dtype must be RS_F32)");
   RS_CHECK_ARG(p->controller == RS_CTRL_DISCRETE, "rollout drives the discrete controller");
   RS_CHECK_ARG(b->num_envs >= 1, "num_envs must be >= 1");
+  RS_CHECK_ARG((int64_t)b->num_envs * b->robots < (int64_t)1 << 31, "num_envs * robots must be < 2^31");
   RS_CHECK_ARG(b->robots >= 2 && 2 * b->robots + 4 <= 32,
                "rollout needs 2 <= robots and 2*robots+4 <= 32 (got %d)", b->robots);
   RS_CHECK_ARG(horizon >= 1, "horizon must be >= 1");

@@ -64,55 +64,59 @@ __device__ __forceinline__ void integrate(const SimConst<T> &C, T c, T s, T v, T
 // the group draws the same candidate for robot r; lanes j < r test it against
 // their own point; the first candidate nobody rejects is kept by lane r.
 template <typename T, int G>
-__device__ void place_points(const SimConst<T> &C, uint32_t env_id, uint32_t episode,
-                             uint32_t purpose, int i, int N, int lane, int64_t &X, int64_t &Y) {
+__device__ void place_points(ConstRef<T> K, uint32_t env_id, uint32_t episode, uint32_t purpose,
+                             int i, int N, int lane, int64_t &X, int64_t &Y) {
+  const auto *P = K.get();
+  const int64_t xlo = P->xlo, ylo = P->ylo, wx = P->wx, wy = P->wy, sep2 = P->sep2;
+  const int64_t xhi = P->xhi, yhi = P->yhi;
+  const uint32_t key0 = P->key0, key1 = P->key1;
   X = 0;
   Y = 0;
   for (int r = 0; r < N; ++r) {
     bool placed = false;
     for (uint32_t att = 0; att < 64u && !placed; ++att) {
-      const uint4 o = stream_block(C.key0, C.key1, env_id, episode, purpose, (uint32_t)r, att);
-      const int64_t cx = C.xlo + (int64_t)(((uint64_t)o.x * (uint64_t)C.wx) >> 32);
-      const int64_t cy = C.ylo + (int64_t)(((uint64_t)o.y * (uint64_t)C.wy) >> 32);
+      const uint4 o = stream_block(key0, key1, env_id, episode, purpose, (uint32_t)r, att);
+      const int64_t cx = xlo + (int64_t)(((uint64_t)o.x * (uint64_t)wx) >> 32);
+      const int64_t cy = ylo + (int64_t)(((uint64_t)o.y * (uint64_t)wy) >> 32);
       const int64_t ddx = cx - X, ddy = cy - Y;
-      const bool clash = (i < r) && (ddx * ddx + ddy * ddy < C.sep2);
+      const bool clash = (i < r) && (ddx * ddx + ddy * ddy < sep2);
       if (!group_any<G>(clash, lane)) {
         placed = true;
         if (i == r) { X = cx; Y = cy; }
       }
     }
-    for (int64_t cy = C.ylo; cy <= C.yhi && !placed; cy += 500) {
-      for (int64_t cx = C.xlo; cx <= C.xhi && !placed; cx += 500) {
+    for (int64_t cy = ylo; cy <= yhi && !placed; cy += 500) {
+      for (int64_t cx = xlo; cx <= xhi && !placed; cx += 500) {
         const int64_t ddx = cx - X, ddy = cy - Y;
-        const bool clash = (i < r) && (ddx * ddx + ddy * ddy < C.sep2);
+        const bool clash = (i < r) && (ddx * ddx + ddy * ddy < sep2);
         if (!group_any<G>(clash, lane)) {
           placed = true;
           if (i == r) { X = cx; Y = cy; }
         }
       }
     }
-    if (!placed && i == r) { X = C.xlo; Y = C.ylo; }
+    if (!placed && i == r) { X = xlo; Y = ylo; }
   }
 }
 
-// Reset sampler for the group's environment (episode `episode`). Kept out of
-// line: it is the cold path of a step, and inlined it would hold registers
-// across the whole step loop. The constants are taken by value: a reference
-// would make the kernel keep its whole argument block in scratch memory.
+// Reset sampler for the group's environment (episode `episode`). Its
+// constants (lattice, separation, stream key) are loaded from the kernel
+// arguments where they are used: it is the cold path of a step.
 template <typename T, int G>
-__device__ void reset_env(const SimConst<T> C, uint32_t env_id,
-                                                    uint32_t episode, int i, int N, int lane, T &x,
-                                                    T &y, T &th, T &gx, T &gy) {
+__device__ void reset_env(ConstRef<T> K, uint32_t env_id, uint32_t episode, int i, int N,
+                          int lane, T &x, T &y, T &th, T &gx, T &gy) {
   int64_t X, Y, GX, GY;
-  place_points<T, G>(C, env_id, episode, kPose, i, N, lane, X, Y);
-  place_points<T, G>(C, env_id, episode, kGoal, i, N, lane, GX, GY);
-  const uint4 hb = stream_block(C.key0, C.key1, env_id, episode, kHeading, (uint32_t)(i >> 2), 0u);
+  place_points<T, G>(K, env_id, episode, kPose, i, N, lane, X, Y);
+  place_points<T, G>(K, env_id, episode, kGoal, i, N, lane, GX, GY);
+  const auto *P = K.get();
+  const double grid = P->grid;
+  const uint4 hb = stream_block(P->key0, P->key1, env_id, episode, kHeading, (uint32_t)(i >> 2), 0u);
   const double u = (double)(word(hb, i & 3) >> 8) * 5.9604644775390625e-8;
   th = (T)(-kPiD + 2.0 * kPiD * u);
-  x = (T)((double)X * C.grid);
-  y = (T)((double)Y * C.grid);
-  gx = (T)((double)GX * C.grid);
-  gy = (T)((double)GY * C.grid);
+  x = (T)((double)X * grid);
+  y = (T)((double)Y * grid);
+  gx = (T)((double)GX * grid);
+  gy = (T)((double)GY * grid);
 }
 
 // Observation of robot i: x, y, cos th, sin th, (x_j - x_i, y_j - y_i) for
@@ -181,8 +185,8 @@ template <typename T> struct StepOut {
 // are group-uniform and updated. Observation of the post-step state is left
 // to the caller (c, s are refreshed).
 template <typename T, int G>
-__device__ StepOut<T> env_step_group(const SimConst<T> &C, QPScratch<T, G> *sh, int lane, int i,
-                                     int N, bool on, uint32_t env_id, int action, T &x, T &y,
+__device__ StepOut<T> env_step_group(const SimConst<T> &C, ConstRef<T> K, QPScratch<T, G> *sh,
+                                     int lane, int i, int N, bool on, uint32_t env_id, int action, T &x, T &y,
                                      T &th, T &c, T &s, T &gx, T &gy, int &step, int &episode,
                                      bool want_viol) {
   StepOut<T> out;
@@ -222,7 +226,7 @@ __device__ StepOut<T> env_step_group(const SimConst<T> &C, QPScratch<T, G> *sh, 
     episode += 1;
     step = 0;
     T nx, ny, nth, ngx, ngy;
-    reset_env<T, G>(C, env_id, (uint32_t)episode, i, N, lane, nx, ny, nth, ngx, ngy);
+    reset_env<T, G>(K, env_id, (uint32_t)episode, i, N, lane, nx, ny, nth, ngx, ngy);
     if (on) { x = nx; y = ny; th = nth; gx = ngx; gy = ngy; }
   }
   sincos_t(th, &s, &c);
