@@ -27,8 +27,10 @@
 namespace rs {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef short shortx8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float floatx2 __attribute__((ext_vector_type(2)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef short shortx2 __attribute__((ext_vector_type(2)));
 
 constexpr int kRollBlock = 256;
 constexpr int kRollWaves = kRollBlock / 64;
@@ -53,13 +55,31 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// ReLU of eight bf16 values with packed 16-bit integer max: a bf16 with the
-// sign bit set is a negative int16, so max(., 0) zeroes exactly the negative
-// values (and -0). Rounding commutes with ReLU, so this equals rounding the
-// FP32 ReLU.
-__device__ __forceinline__ bf16x8 relu_bf16x8(bf16x8 v) {
-  const shortx8 z = {0, 0, 0, 0, 0, 0, 0, 0};
-  return __builtin_bit_cast(bf16x8, __builtin_elementwise_max(__builtin_bit_cast(shortx8, v), z));
+// ReLU of a bf16 pair with a packed 16-bit integer max: a bf16 with the sign
+// bit set is a negative int16, so max(., 0) zeroes exactly the negative values
+// (and -0). Rounding commutes with ReLU, so this equals rounding the FP32 ReLU.
+__device__ __forceinline__ bf16x2 relu_bf16x2(bf16x2 p) {
+  const shortx2 z = {0, 0};
+  return __builtin_bit_cast(bf16x2, __builtin_elementwise_max(__builtin_bit_cast(shortx2, p), z));
+}
+
+// Eight FP32 values rounded to bf16 (round to nearest even), one
+// v_cvt_pk_bf16_f32 per pair, optionally followed by the pairwise ReLU.
+template <bool RELU>
+__device__ __forceinline__ bf16x8 pack_bf16x8(floatx4 a, floatx4 b) {
+  bf16x2 p0 = __builtin_convertvector((floatx2){a[0], a[1]}, bf16x2);
+  bf16x2 p1 = __builtin_convertvector((floatx2){a[2], a[3]}, bf16x2);
+  bf16x2 p2 = __builtin_convertvector((floatx2){b[0], b[1]}, bf16x2);
+  bf16x2 p3 = __builtin_convertvector((floatx2){b[2], b[3]}, bf16x2);
+  if constexpr (RELU) {
+    p0 = relu_bf16x2(p0);
+    p1 = relu_bf16x2(p1);
+    p2 = relu_bf16x2(p2);
+    p3 = relu_bf16x2(p3);
+  }
+  return __builtin_shufflevector(__builtin_shufflevector(p0, p1, 0, 1, 2, 3),
+                                 __builtin_shufflevector(p2, p3, 0, 1, 2, 3), 0, 1, 2, 3, 4, 5,
+                                 6, 7);
 }
 
 // Hidden index held in slot j of lane group g at k-step s of layers 2 and 3:
@@ -196,15 +216,20 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
       if ((D & 3) == 0) {
         const float4 f0 = reinterpret_cast<const float4 *>(src)[0];
         const float4 f1 = reinterpret_cast<const float4 *>(src)[1];
-        xb[0] = (__bf16)f0.x; xb[1] = (__bf16)f0.y; xb[2] = (__bf16)f0.z; xb[3] = (__bf16)f0.w;
-        xb[4] = (__bf16)f1.x; xb[5] = (__bf16)f1.y; xb[6] = (__bf16)f1.z; xb[7] = (__bf16)f1.w;
+        xb = pack_bf16x8<false>((floatx4){f0.x, f0.y, f0.z, f0.w},
+                                 (floatx4){f1.x, f1.y, f1.z, f1.w});
       } else {
+        floatx4 fa, fb;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < 2; ++j) {
           const float2 f = reinterpret_cast<const float2 *>(src)[j];
-          xb[2 * j] = (__bf16)f.x;
-          xb[2 * j + 1] = (__bf16)f.y;
+          const float2 g = reinterpret_cast<const float2 *>(src)[j + 2];
+          fa[2 * j] = f.x;
+          fa[2 * j + 1] = f.y;
+          fb[2 * j] = g.x;
+          fb[2 * j + 1] = g.y;
         }
+        xb = pack_bf16x8<false>(fa, fb);
       }
       floatx4 h1[4];
 #pragma unroll
@@ -215,11 +240,7 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
       }
       bf16x8 hb[2];
 #pragma unroll
-      for (int sk = 0; sk < 2; ++sk) {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) hb[sk][j] = (__bf16)h1[2 * sk + (j >> 2)][j & 3];
-        hb[sk] = relu_bf16x8(hb[sk]);
-      }
+      for (int sk = 0; sk < 2; ++sk) hb[sk] = pack_bf16x8<true>(h1[2 * sk], h1[2 * sk + 1]);
       floatx4 h2[4];
 #pragma unroll
       for (int mo = 0; mo < 4; ++mo) {
@@ -230,11 +251,7 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
       }
       bf16x8 hc[2];
 #pragma unroll
-      for (int sk = 0; sk < 2; ++sk) {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) hc[sk][j] = (__bf16)h2[2 * sk + (j >> 2)][j & 3];
-        hc[sk] = relu_bf16x8(hc[sk]);
-      }
+      for (int sk = 0; sk < 2; ++sk) hc[sk] = pack_bf16x8<true>(h2[2 * sk], h2[2 * sk + 1]);
       floatx4 lg = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3f[0], hc[0], b3f, 0, 0, 0);
       lg = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3f[1], hc[1], lg, 0, 0, 0);
       // lane (g, c16) holds logits 4g..4g+3 of robot n
