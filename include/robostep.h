@@ -198,7 +198,7 @@ rs_status rollout(rs_ctx *ctx, const rs_params *p, const rs_batch *b, const rs_p
  * mixed batch are laid out env after env (robot_offset = prefix sum).
  * ------------------------------------------------------------------------- */
 typedef struct {
-  int32_t block_threads;     /* 64..1024, multiple of 64; 0 = 256 */
+  int32_t block_threads;     /* 64..256, multiple of 64; 0 = 256 */
   int32_t lanes_per_env[17]; /* indexed by N: power of two >= N, <= 16; 0 = smallest */
   int32_t qp_iters[17];      /* indexed by N: active-set iteration cap; 0 = 8N+32 */
 } rs_schedule;
@@ -235,16 +235,19 @@ rs_status env_run(rs_ctx *ctx, const rs_params *p, const rs_plan *plan, const rs
 int64_t rs_plan_obs_offset(const rs_plan *plan, int32_t env);
 
 /* ---------------------------------------------------------------------------
- * Autotuner: for each robot count N in `robots` (host [count]), run env_run on
- * `envs` synthetic envs (half drawn by the reset sampler, half packed in a
- * tight cluster so the certificate binds) for `steps` steps under each
- * candidate schedule: lanes per env (envs per wavefront = 64 / lanes) in
- * {smallest power of two >= N, twice that <= 16}, block size in {64, 128,
- * 256}, active-set iteration cap in {2N+4, 4N+8, 8N+32}. A candidate is
- * admissible when every final position matches the widest-cap reference
- * within steps * dt * tol (tol in m/s); the fastest admissible one is kept
- * per N in the context's schedule table (used by plans created afterwards
- * with schedule NULL) and returned in `out` (may be NULL).
+ * Autotuner: builds the mixed workload of `envs` synthetic envs of every robot
+ * count in `robots` (host [count], each 2..16; half drawn by the reset
+ * sampler, half packed in a tight cluster so the certificate binds) and times
+ * env_run over `steps` steps (best of 3) under candidate schedules, by
+ * coordinate descent from the default schedule: block size in {64, 128, 256},
+ * then per size lanes per env (envs per wavefront = 64 / lanes) doubled,
+ * then the active-set iteration cap in {2N+4, 4N+8}. A change is kept when
+ * every final position matches the default-schedule, widest-cap reference
+ * within steps * dt * tol (tol in m/s) and it is at least 2% faster, so the
+ * result is never slower than the default on this workload. The schedule is
+ * stored in the context (used by plans created afterwards with schedule NULL)
+ * and returned in `out` (may be NULL). Allocates device scratch for the
+ * workload; RS_ERR_OUT_OF_MEMORY if that fails.
  * ------------------------------------------------------------------------- */
 rs_status rs_autotune(rs_ctx *ctx, const rs_params *p, const int32_t *robots, int32_t count,
                       int32_t envs, int32_t steps, double tol, rs_schedule *out);

@@ -351,130 +351,164 @@ rs_status rs_autotune(rs_ctx *ctx, const rs_params *p, const int32_t *robots, in
   if (s != RS_OK) return s;
   RS_CHECK_ARG(p->dtype == RS_F32 && p->controller == RS_CTRL_DISCRETE,
                "autotune runs the FP32 discrete-controller path");
+  for (int32_t k = 0; k < count; ++k)
+    RS_CHECK_ARG(robots[k] >= 2 && robots[k] <= RS_MAX_ROBOTS, "robots[%d] = %d outside 2..16",
+                 k, robots[k]);
+  // the mixed workload: `envs` envs of every listed size, interleaved
+  const int64_t E64 = (int64_t)envs * count;
+  RS_CHECK_ARG(E64 < (1 << 24), "envs * count too large for the autotuner");
+  const int32_t E = (int32_t)E64;
+  std::vector<int32_t> counts(E);
+  for (int32_t e = 0; e < E; ++e) counts[e] = robots[e % count];
+  size_t R = 0;
+  for (int32_t e = 0; e < E; ++e) R += (size_t)counts[e];
+
   hipStream_t st;
   RS_CHECK_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
   hipEvent_t ev0, ev1;
-  RS_CHECK_HIP(hipEventCreate(&ev0));
-  RS_CHECK_HIP(hipEventCreate(&ev1));
+  (void)hipEventCreate(&ev0);
+  (void)hipEventCreate(&ev1);
+  float *dbuf = nullptr;
+  int32_t *ibuf = nullptr;
   rs_status result = RS_OK;
-  for (int32_t k = 0; k < count && result == RS_OK; ++k) {
-    const int n = robots[k];
-    if (n < 2 || n > RS_MAX_ROBOTS) {
-      set_error("robots[%d] = %d outside 2..16", k, n);
-      result = RS_ERR_INVALID_ARG;
-      break;
-    }
-    const size_t R = (size_t)envs * n;
-    // synthetic workload: reset-sampled envs, and every other env packed in a
-    // cluster of pitch 0.2 m around the arena centre so the certificate binds
-    std::vector<float> hx(R), hy(R), hth(R), hgx(R), hgy(R);
-    float *dbuf = nullptr;
-    int32_t *ibuf = nullptr;
-    if (hipMalloc(&dbuf, 10 * R * sizeof(float)) != hipSuccess ||
-        hipMalloc(&ibuf, 2 * (size_t)envs * sizeof(int32_t)) != hipSuccess) {
-      set_error("autotune allocation failed");
-      result = RS_ERR_OUT_OF_MEMORY;
-      break;
-    }
-    rs_batch b;
-    std::memset(&b, 0, sizeof(b));
-    b.num_envs = envs;
-    b.robots = n;
-    float *f = dbuf;
-    b.x = f; b.y = f + R; b.theta = f + 2 * R; b.goal_x = f + 3 * R; b.goal_y = f + 4 * R;
-    float *init = f + 5 * R;  // pristine copy of the 5 fields
-    b.step = ibuf;
-    b.episode = ibuf + envs;
-    std::vector<int32_t> counts(envs, n);
-    rs_schedule ref_s;
-    default_schedule(ref_s);
-    rs_plan *ref_plan = nullptr;
-    s = rs_plan_create(ctx, envs, counts.data(), &ref_s, &ref_plan);
-    if (s != RS_OK) { result = s; (void)hipFree(dbuf); (void)hipFree(ibuf); break; }
-    (void)hipMemsetAsync(ibuf, 0, 2 * (size_t)envs * sizeof(int32_t), st);
-    s = env_reset_mixed(ctx, p, ref_plan, &b, nullptr, st);
-    (void)hipStreamSynchronize(st);
-    (void)hipMemcpy(hx.data(), b.x, R * 4, hipMemcpyDeviceToHost);
-    (void)hipMemcpy(hy.data(), b.y, R * 4, hipMemcpyDeviceToHost);
-    const int side = (int)std::ceil(std::sqrt((double)n));
-    for (int32_t e = 1; e < envs; e += 2) {
-      for (int i = 0; i < n; ++i) {
-        hx[(size_t)e * n + i] = -0.3f + 0.2f * (float)(i % side);
-        hy[(size_t)e * n + i] = -0.3f + 0.2f * (float)(i / side);
+  if (hipMalloc(&dbuf, 10 * R * sizeof(float)) != hipSuccess ||
+      hipMalloc(&ibuf, 2 * (size_t)E * sizeof(int32_t)) != hipSuccess) {
+    set_error("autotune allocation failed");
+    result = RS_ERR_OUT_OF_MEMORY;
+  }
+  rs_batch b;
+  std::memset(&b, 0, sizeof(b));
+  float *init = dbuf ? dbuf + 5 * R : nullptr;  // pristine copy of the 5 fields
+  std::vector<float> rx(R), ry(R), cx(R), cy(R);
+  auto restore = [&]() {
+    (void)hipMemcpyAsync(dbuf, init, 5 * R * 4, hipMemcpyDeviceToDevice, st);
+    (void)hipMemsetAsync(ibuf, 0, 2 * (size_t)E * sizeof(int32_t), st);
+  };
+  // run `sched` (min over reps) and check it against the reference positions
+  auto measure = [&](const rs_schedule &sched, bool check, float &ms) -> bool {
+    rs_plan *pl = nullptr;
+    if (rs_plan_create(ctx, E, counts.data(), &sched, &pl) != RS_OK) return false;
+    ms = 1e30f;
+    bool ok = true;
+    for (int rep = 0; rep < 3 && ok; ++rep) {
+      restore();
+      (void)hipEventRecord(ev0, st);
+      if (env_run(ctx, p, pl, &b, steps, nullptr, 0, nullptr, nullptr, nullptr, nullptr, nullptr,
+                  st) != RS_OK) {
+        ok = false;
+        break;
+      }
+      (void)hipEventRecord(ev1, st);
+      (void)hipEventSynchronize(ev1);
+      float t = 0.f;
+      (void)hipEventElapsedTime(&t, ev0, ev1);
+      ms = std::min(ms, t);
+      if (rep == 0 && check) {
+        (void)hipMemcpy(cx.data(), b.x, R * 4, hipMemcpyDeviceToHost);
+        (void)hipMemcpy(cy.data(), b.y, R * 4, hipMemcpyDeviceToHost);
+        const double bound = steps * p->dt * tol;
+        double worst = 0.0;
+        for (size_t q = 0; q < R; ++q)
+          worst = std::max(worst, (double)std::max(std::fabs(cx[q] - rx[q]), std::fabs(cy[q] - ry[q])));
+        ok = worst <= bound;
       }
     }
-    (void)hipMemcpy(b.x, hx.data(), R * 4, hipMemcpyHostToDevice);
-    (void)hipMemcpy(b.y, hy.data(), R * 4, hipMemcpyHostToDevice);
-    (void)hipMemcpy(init, dbuf, 5 * R * 4, hipMemcpyDeviceToDevice);
-    auto restore = [&]() {
-      (void)hipMemcpyAsync(dbuf, init, 5 * R * 4, hipMemcpyDeviceToDevice, st);
-      (void)hipMemsetAsync(ibuf, 0, 2 * (size_t)envs * sizeof(int32_t), st);
-    };
-    // reference: smallest lanes, widest cap
-    ref_s.qp_iters[n] = 8 * n + 32;
-    rs_plan_destroy(ref_plan);
-    ref_plan = nullptr;
-    rs_plan_create(ctx, envs, counts.data(), &ref_s, &ref_plan);
-    restore();
-    env_run(ctx, p, ref_plan, &b, steps, nullptr, 0, nullptr, nullptr, nullptr, nullptr, nullptr, st);
-    (void)hipStreamSynchronize(st);
-    std::vector<float> rx(R), ry(R), cx(R), cy(R);
-    (void)hipMemcpy(rx.data(), b.x, R * 4, hipMemcpyDeviceToHost);
-    (void)hipMemcpy(ry.data(), b.y, R * 4, hipMemcpyDeviceToHost);
-    rs_plan_destroy(ref_plan);
-    const double bound = steps * p->dt * tol;
-    const int g0 = pow2_group(n);
-    float best_ms = 1e30f;
-    int best_g = g0, best_block = 256, best_cap = 8 * n + 32;
-    const int caps[3] = {2 * n + 4, 4 * n + 8, 8 * n + 32};
-    for (int g = g0; g <= 16; g *= 2) {
-      if (g > g0 * 2) break;
-      for (int blk = 64; blk <= 256; blk *= 2) {
-        for (int ci = 0; ci < 3; ++ci) {
-          rs_schedule cs;
-          default_schedule(cs);
-          cs.block_threads = blk;
-          cs.lanes_per_env[n] = g;
-          cs.qp_iters[n] = caps[ci];
-          rs_plan *pl = nullptr;
-          if (rs_plan_create(ctx, envs, counts.data(), &cs, &pl) != RS_OK) continue;
-          float ms = 1e30f;
-          bool ok = true;
-          for (int rep = 0; rep < 3 && ok; ++rep) {
-            restore();
-            (void)hipEventRecord(ev0, st);
-            env_run(ctx, p, pl, &b, steps, nullptr, 0, nullptr, nullptr, nullptr, nullptr, nullptr, st);
-            (void)hipEventRecord(ev1, st);
-            (void)hipEventSynchronize(ev1);
-            float t = 0.f;
-            (void)hipEventElapsedTime(&t, ev0, ev1);
-            ms = std::min(ms, t);
-            if (rep == 0) {
-              (void)hipMemcpy(cx.data(), b.x, R * 4, hipMemcpyDeviceToHost);
-              (void)hipMemcpy(cy.data(), b.y, R * 4, hipMemcpyDeviceToHost);
-              double worst = 0.0;
-              for (size_t q = 0; q < R; ++q)
-                worst = std::max(worst, (double)std::max(std::fabs(cx[q] - rx[q]),
-                                                         std::fabs(cy[q] - ry[q])));
-              ok = worst <= bound;
-            }
-          }
-          rs_plan_destroy(pl);
-          if (ok && ms < best_ms * 0.98f) {
-            best_ms = ms;
-            best_g = g;
-            best_block = blk;
-            best_cap = caps[ci];
+    rs_plan_destroy(pl);
+    return ok;
+  };
+
+  rs_schedule best;
+  default_schedule(best);
+  if (result == RS_OK) {
+    float *f = dbuf;
+    b.num_envs = E;
+    b.robots = 0;
+    b.x = f; b.y = f + R; b.theta = f + 2 * R; b.goal_x = f + 3 * R; b.goal_y = f + 4 * R;
+    b.step = ibuf;
+    b.episode = ibuf + E;
+    // start states: the reset sampler for every other env, a tight cluster of
+    // pitch 0.2 m around the arena centre (the certificate binds) for the rest
+    rs_plan *ref_plan = nullptr;
+    result = rs_plan_create(ctx, E, counts.data(), &best, &ref_plan);
+    if (result == RS_OK) {
+      (void)hipMemsetAsync(ibuf, 0, 2 * (size_t)E * sizeof(int32_t), st);
+      result = env_reset_mixed(ctx, p, ref_plan, &b, nullptr, st);
+      (void)hipStreamSynchronize(st);
+      std::vector<float> hx(R), hy(R);
+      (void)hipMemcpy(hx.data(), b.x, R * 4, hipMemcpyDeviceToHost);
+      (void)hipMemcpy(hy.data(), b.y, R * 4, hipMemcpyDeviceToHost);
+      size_t off = 0;
+      for (int32_t e = 0; e < E; ++e) {
+        const int n = counts[e];
+        if (e & 1) {
+          const int side = (int)std::ceil(std::sqrt((double)n));
+          for (int i = 0; i < n; ++i) {
+            hx[off + i] = -0.3f + 0.2f * (float)(i % side);
+            hy[off + i] = -0.3f + 0.2f * (float)(i / side);
           }
         }
+        off += (size_t)n;
       }
+      (void)hipMemcpy(b.x, hx.data(), R * 4, hipMemcpyHostToDevice);
+      (void)hipMemcpy(b.y, hy.data(), R * 4, hipMemcpyHostToDevice);
+      (void)hipMemcpy(init, dbuf, 5 * R * 4, hipMemcpyDeviceToDevice);
+      rs_plan_destroy(ref_plan);
     }
-    ctx->sched.lanes_per_env[n] = best_g;
-    ctx->sched.qp_iters[n] = best_cap;
-    ctx->sched.block_threads = best_block;
-    (void)hipFree(dbuf);
-    (void)hipFree(ibuf);
+    // reference positions: the default schedule with the widest iteration cap
+    rs_schedule ref = best;
+    for (int32_t k = 0; k < count; ++k) ref.qp_iters[robots[k]] = 8 * robots[k] + 32;
+    float ref_ms = 0.f;
+    if (result == RS_OK && measure(ref, false, ref_ms)) {
+      (void)hipMemcpy(rx.data(), b.x, R * 4, hipMemcpyDeviceToHost);
+      (void)hipMemcpy(ry.data(), b.y, R * 4, hipMemcpyDeviceToHost);
+    } else if (result == RS_OK) {
+      result = RS_ERR_DEVICE;
+    }
+    // coordinate descent from the default schedule: block size, then lanes
+    // per env and iteration cap size by size; a change is kept only when it
+    // passes the check and is at least 2% faster than the best so far
+    float best_ms = 0.f;
+    if (result == RS_OK && !measure(best, true, best_ms)) result = RS_ERR_DEVICE;
+    auto consider = [&](const rs_schedule &cand) {
+      float ms = 0.f;
+      if (measure(cand, true, ms) && ms < 0.98f * best_ms) {
+        best = cand;
+        best_ms = ms;
+      }
+    };
+    if (result == RS_OK) {
+      for (int blk = 64; blk <= 256; blk *= 2) {
+        if (blk == best.block_threads) continue;
+        rs_schedule c = best;
+        c.block_threads = blk;
+        consider(c);
+      }
+      for (int32_t k = 0; k < count; ++k) {
+        const int n = robots[k];
+        const int g0 = pow2_group(n);
+        if (2 * g0 <= 16) {
+          rs_schedule c = best;
+          c.lanes_per_env[n] = 2 * g0;
+          consider(c);
+        }
+        const int caps[2] = {2 * n + 4, 4 * n + 8};
+        for (int ci = 0; ci < 2; ++ci) {
+          rs_schedule c = best;
+          c.qp_iters[n] = caps[ci];
+          consider(c);
+        }
+      }
+      // report the effective values for the tuned sizes
+      for (int32_t k = 0; k < count; ++k) {
+        const int n = robots[k];
+        best.lanes_per_env[n] = lanes_for(best, n);
+        if (best.qp_iters[n] <= 0) best.qp_iters[n] = 8 * n + 32;
+      }
+      ctx->sched = best;
+    }
   }
+  if (dbuf) (void)hipFree(dbuf);
+  if (ibuf) (void)hipFree(ibuf);
   (void)hipEventDestroy(ev0);
   (void)hipEventDestroy(ev1);
   (void)hipStreamDestroy(st);
