@@ -140,7 +140,8 @@ template <int CTRL> __device__ __forceinline__ double dpp(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Value held by lane (i + K) mod G of the caller's group (1 <= K < G).
+// Value held by lane (i + K) mod G of the caller's group (1 <= K < G). Every
+// lane of the group must be active.
 template <int G, int K, typename T> __device__ __forceinline__ T grot(T v, int lane) {
   static_assert(K >= 1 && K < G, "rotation inside the group");
   if constexpr (G == 2) {
@@ -149,10 +150,16 @@ template <int G, int K, typename T> __device__ __forceinline__ T grot(T v, int l
     return dpp<(K == 1 ? 0x39 : (K == 2 ? 0x4E : 0x93))>(v);
   } else if constexpr (G == 16) {
     return dpp<0x120 + (16 - K)>(v);
-  } else {  // G == 8: two rotations of the 16-lane row, pick the one in-group
-    const T a = dpp<0x120 + (16 - K)>(v);  // lane l + K
-    const T b = dpp<0x120 + (8 - K)>(v);   // lane l + K - 8
-    return ((lane & 7) + K < 8) ? a : b;
+  } else {  // G == 8: no single DPP rotates within 8 lanes; permute by LDS
+    const int addr = ((lane & ~7) | ((lane + K) & 7)) << 2;
+    if constexpr (sizeof(T) == 4) {
+      return __builtin_bit_cast(T, __builtin_amdgcn_ds_bpermute(addr, __builtin_bit_cast(int, v)));
+    } else {
+      const long long b = __builtin_bit_cast(long long, v);
+      const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)(b & 0xffffffffll));
+      const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(b >> 32));
+      return __builtin_bit_cast(T, ((long long)hi << 32) | (unsigned int)lo);
+    }
   }
 }
 

@@ -1003,13 +1003,29 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, const SimConst<T> &C, int lane, 
             for (int k = 0; k < 4; ++k) acc += cc[k] * tclamp(un[k] - lm * cc[k], lo[k], hi[k]);
             return acc;
           };
-          // largest breakpoint (or 0) where phi is still positive
+          // largest breakpoint (or 0) where phi is still positive; the eight
+          // breakpoints are shared out over the group's lanes and the best
+          // one found by a butterfly (equal breakpoints give equal phi)
           T llo = T(0), plo = phi(T(0));
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const T p1 = phi(e1[k]), p2 = phi(e2[k]);
-            if (p1 > T(0) && e1[k] > llo) { llo = e1[k]; plo = p1; }
-            if (p2 > T(0) && e2[k] > llo) { llo = e2[k]; plo = p2; }
+          {
+            T bl = T(-1), bv = T(0);
+            for (int b = i; b < 8; b += G) {
+              const int k = b >> 1;
+              const T ek = (b & 1) ? (k == 0 ? e2[0] : k == 1 ? e2[1] : k == 2 ? e2[2] : e2[3])
+                                   : (k == 0 ? e1[0] : k == 1 ? e1[1] : k == 2 ? e1[2] : e1[3]);
+              const T pk = phi(ek);
+              if (pk > T(0) && ek > bl) { bl = ek; bv = pk; }
+            }
+            auto merge = [&](auto cc) {
+              constexpr int CT = decltype(cc)::value;
+              const T w = dpp<CT>(bl), q = dpp<CT>(bv);
+              if (w > bl) { bl = w; bv = q; }
+            };
+            merge(std::integral_constant<int, 0xB1>{});
+            if constexpr (G >= 4) merge(std::integral_constant<int, 0x4E>{});
+            if constexpr (G >= 8) merge(std::integral_constant<int, 0x141>{});
+            if constexpr (G >= 16) merge(std::integral_constant<int, 0x140>{});
+            if (bl > llo) { llo = bl; plo = bv; }
           }
           // slope of -phi just right of llo: coordinates still free there
           T slope = T(0);
