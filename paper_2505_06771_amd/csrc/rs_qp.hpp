@@ -970,87 +970,92 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, const SimConst<T> &C, int lane, 
       const bool two = nv == 2 && id2 >= 0;
       const int pa = bid >> 4, pb = bid & 15;
       const int qa = two ? id2 >> 4 : pa, qb = two ? id2 & 15 : pb;
-      const bool disjoint = qa != pa && qa != pb && qb != pa && qb != pb;
+      const bool shared = two && (qa == pa || qa == pb || qb == pa || qb == pb);
       bool ok = true;
       T lam1 = T(0), lam2 = T(0);
-      if (!two || disjoint) {
-        // projection onto box & one half-space for each row, on its own two
-        // robots; rows one after the other (a true loop keeps the registers
-        // of one row), each committing its robots' commands in their lanes
+      T nux = ux, nuy = uy;  // my command under the guess (u0 unless I move)
+      // projection onto box & one half-space for each row, on its own two
+      // robots; rows one after the other (a true loop keeps the registers of
+      // one row) with a trip count uniform over the wavefront
+      const int trips = __ballot(two && !shared) ? 2 : 1;
 #pragma unroll 1
-        for (int rr = 0; rr < (two ? 2 : 1); ++rr) {
-          const bool r2 = rr == 1;
-          const int ra = r2 ? qa : pa, rb = r2 ? qb : pb;
-          const T dx = r2 ? e2x : bdx, dy = r2 ? e2y : bdy;
-          const T beta = r2 ? beta2 : bbb;
-          const int la = gbase + ra, lb = gbase + rb;
-          const T cc[4] = {T(-2) * dx, T(-2) * dy, T(2) * dx, T(2) * dy};
-          const T un[4] = {__shfl(uhx, la, 64), __shfl(uhy, la, 64), __shfl(uhx, lb, 64),
-                           __shfl(uhy, lb, 64)};
-          T lo[4], hi[4];
-          wall_bounds(C, __shfl(px, la, 64), __shfl(py, la, 64), lo[0], hi[0], lo[1], hi[1]);
-          wall_bounds(C, __shfl(px, lb, 64), __shfl(py, lb, 64), lo[2], hi[2], lo[3], hi[3]);
-          T e1[4], e2[4];  // multiplier values where coordinate k meets hi_k / lo_k
+      for (int rr = 0; rr < trips; ++rr) {
+        const bool r2 = rr == 1;
+        const bool use = !shared && (!r2 || two);  // this group solves this row
+        const int ra = r2 ? qa : pa, rb = r2 ? qb : pb;
+        const T dx = r2 ? e2x : bdx, dy = r2 ? e2y : bdy;
+        const T beta = r2 ? beta2 : bbb;
+        const int la = gbase + ra, lb = gbase + rb;
+        const T cc[4] = {T(-2) * dx, T(-2) * dy, T(2) * dx, T(2) * dy};
+        const T un[4] = {__shfl(uhx, la, 64), __shfl(uhy, la, 64), __shfl(uhx, lb, 64),
+                         __shfl(uhy, lb, 64)};
+        T lo[4], hi[4];
+        wall_bounds(C, __shfl(px, la, 64), __shfl(py, la, 64), lo[0], hi[0], lo[1], hi[1]);
+        wall_bounds(C, __shfl(px, lb, 64), __shfl(py, lb, 64), lo[2], hi[2], lo[3], hi[3]);
+        T e1[4], e2[4];  // multiplier values where coordinate k meets hi_k / lo_k
 #pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const T r = cc[k] != T(0) ? qdiv(T(1), cc[k]) : T(0);
-            e1[k] = (un[k] - hi[k]) * r;
-            e2[k] = (un[k] - lo[k]) * r;
-          }
-          auto phi = [&](T lm) {
-            T acc = -beta;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) acc += cc[k] * tclamp(un[k] - lm * cc[k], lo[k], hi[k]);
-            return acc;
-          };
-          // largest breakpoint (or 0) where phi is still positive; the eight
-          // breakpoints are shared out over the group's lanes and the best
-          // one found by a butterfly (equal breakpoints give equal phi)
-          T llo = T(0), plo = phi(T(0));
-          {
-            T bl = T(-1), bv = T(0);
-            for (int b = i; b < 8; b += G) {
-              const int k = b >> 1;
-              const T ek = (b & 1) ? (k == 0 ? e2[0] : k == 1 ? e2[1] : k == 2 ? e2[2] : e2[3])
-                                   : (k == 0 ? e1[0] : k == 1 ? e1[1] : k == 2 ? e1[2] : e1[3]);
-              const T pk = phi(ek);
-              if (pk > T(0) && ek > bl) { bl = ek; bv = pk; }
-            }
-            auto merge = [&](auto cc) {
-              constexpr int CT = decltype(cc)::value;
-              const T w = dpp<CT>(bl), q = dpp<CT>(bv);
-              if (w > bl) { bl = w; bv = q; }
-            };
-            merge(std::integral_constant<int, 0xB1>{});
-            if constexpr (G >= 4) merge(std::integral_constant<int, 0x4E>{});
-            if constexpr (G >= 8) merge(std::integral_constant<int, 0x141>{});
-            if constexpr (G >= 16) merge(std::integral_constant<int, 0x140>{});
-            if (bl > llo) { llo = bl; plo = bv; }
-          }
-          // slope of -phi just right of llo: coordinates still free there
-          T slope = T(0);
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const bool fr = cc[k] != T(0) && tmin(e1[k], e2[k]) <= llo && llo < tmax(e1[k], e2[k]);
-            slope += fr ? cc[k] * cc[k] : T(0);
-          }
-          ok = ok && slope > T(0);
-          const T lam = tmax(llo + qdiv(plo, tmax(slope, T(1e-30))), T(0));
-          if (i == ra) {
-            ux = tclamp(un[0] - lam * cc[0], lo[0], hi[0]);
-            uy = tclamp(un[1] - lam * cc[1], lo[1], hi[1]);
-          } else if (i == rb) {
-            ux = tclamp(un[2] - lam * cc[2], lo[2], hi[2]);
-            uy = tclamp(un[3] - lam * cc[3], lo[3], hi[3]);
-          }
-          lam2 = r2 ? lam : lam2;
-          lam1 = r2 ? lam1 : lam;
+        for (int k = 0; k < 4; ++k) {
+          const T r = cc[k] != T(0) ? qdiv(T(1), cc[k]) : T(0);
+          e1[k] = (un[k] - hi[k]) * r;
+          e2[k] = (un[k] - lo[k]) * r;
         }
-      } else {
+        auto phi = [&](T lm) {
+          T acc = -beta;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) acc += cc[k] * tclamp(un[k] - lm * cc[k], lo[k], hi[k]);
+          return acc;
+        };
+        // largest breakpoint (or 0) where phi is still positive; the eight
+        // breakpoints are shared out over the group's lanes and the best one
+        // found by a butterfly (equal breakpoints give equal phi)
+        T llo = T(0), plo = phi(T(0));
+        {
+          T bl = T(-1), bv = T(0);
+          for (int b = i; b < 8; b += G) {
+            const int k = b >> 1;
+            const T ek = (b & 1) ? (k == 0 ? e2[0] : k == 1 ? e2[1] : k == 2 ? e2[2] : e2[3])
+                                 : (k == 0 ? e1[0] : k == 1 ? e1[1] : k == 2 ? e1[2] : e1[3]);
+            const T pk = phi(ek);
+            const bool better = pk > T(0) && ek > bl;
+            bl = better ? ek : bl;
+            bv = better ? pk : bv;
+          }
+          auto merge = [&](auto c) {
+            constexpr int CT = decltype(c)::value;
+            const T w = dpp<CT>(bl), q = dpp<CT>(bv);
+            const bool better = w > bl;
+            bl = better ? w : bl;
+            bv = better ? q : bv;
+          };
+          merge(std::integral_constant<int, 0xB1>{});
+          if constexpr (G >= 4) merge(std::integral_constant<int, 0x4E>{});
+          if constexpr (G >= 8) merge(std::integral_constant<int, 0x141>{});
+          if constexpr (G >= 16) merge(std::integral_constant<int, 0x140>{});
+          plo = bl > llo ? bv : plo;
+          llo = bl > llo ? bl : llo;
+        }
+        // slope of -phi just right of llo: coordinates still free there
+        T slope = T(0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const bool fr = cc[k] != T(0) && tmin(e1[k], e2[k]) <= llo && llo < tmax(e1[k], e2[k]);
+          slope += fr ? cc[k] * cc[k] : T(0);
+        }
+        ok = ok && (!use || slope > T(0));
+        const T lam = tmax(llo + qdiv(plo, tmax(slope, T(1e-30))), T(0));
+        const bool ma = use && i == ra, mb = use && i == rb;
+        const T ax = tclamp(un[0] - lam * cc[0], lo[0], hi[0]);
+        const T ay = tclamp(un[1] - lam * cc[1], lo[1], hi[1]);
+        const T bx = tclamp(un[2] - lam * cc[2], lo[2], hi[2]);
+        const T by = tclamp(un[3] - lam * cc[3], lo[3], hi[3]);
+        nux = ma ? ax : (mb ? bx : nux);
+        nuy = ma ? ay : (mb ? by : nuy);
+        lam2 = r2 ? lam : lam2;
+        lam1 = r2 ? lam1 : lam;
+      }
+      if (shared) {
         // two rows through a shared robot r; j is p2's other end. With no
         // bound binding on a, b, j: u = u_nom - lam1 c1 - lam2 c2 there.
-        const int r = (qa == pa || qb == pa) ? pa : pb;
-        const int j = qa == r ? qb : qa;
         const T c1x = i == pa ? T(-2) * bdx : (i == pb ? T(2) * bdx : T(0));
         const T c1y = i == pa ? T(-2) * bdy : (i == pb ? T(2) * bdy : T(0));
         const T c2x = i == qa ? T(-2) * e2x : (i == qb ? T(2) * e2x : T(0));
@@ -1065,12 +1070,12 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, const SimConst<T> &C, int lane, 
         lam1 = (g22 * h1 - g12 * h2) * idet;
         lam2 = (g11 * h2 - g12 * h1) * idet;
         ok = det > T(1e-6) * g11 * g22 && lam1 >= T(0) && lam2 >= T(0);
-        bool out = false;
-        if (i == pa || i == pb || i == j) {
-          ux = uhx - lam1 * c1x - lam2 * c2x;
-          uy = uhy - lam1 * c1y - lam2 * c2y;
-          out = ux < lox || ux > hix || uy < loy || uy > hiy;
-        }
+        const bool mv = i == pa || i == pb || i == qa || i == qb;
+        const T vx = uhx - lam1 * c1x - lam2 * c2x;
+        const T vy = uhy - lam1 * c1y - lam2 * c2y;
+        nux = mv ? vx : nux;
+        nuy = mv ? vy : nuy;
+        const bool out = mv && (vx < lox || vx > hix || vy < loy || vy > hiy);
         ok = ok && !group_any<G>(out, lane);
       }
       // check every row through a moved robot, except the guessed ones
@@ -1080,47 +1085,28 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, const SimConst<T> &C, int lane, 
       for (int m = 0; m < 4; ++m) {
         const int x = mr[m], lx = gbase + x;
         const T pxx = __shfl(px, lx, 64), pyx = __shfl(py, lx, 64);
-        const T uxx = __shfl(ux, lx, 64), uyx = __shfl(uy, lx, 64);
+        const T uxx = __shfl(nux, lx, 64), uyx = __shfl(nuy, lx, 64);
         const bool guessed = (x == pa && i == pb) || (x == pb && i == pa) ||
                              (two && ((x == qa && i == qb) || (x == qb && i == qa)));
-        if (on && x != i && !guessed) {
-          const T dx = pxx - px, dy = pyx - py;
-          const T d2 = dx * dx + dy * dy;
-          const T h = d2 - C.rs2;
-          T sn = T(2) * (dx * (ux - uxx) + dy * (uy - uyx)) - C.gamma * (h * h * h);
-          sn = d2 > T(0) ? sn * (T(0.35355339059327373) * rsqrt_t(d2)) : sn;
-          bad = bad || sn > C.tol_add;
-        }
+        const T dx = pxx - px, dy = pyx - py;
+        const T d2 = dx * dx + dy * dy;
+        const T h = d2 - C.rs2;
+        T sn = T(2) * (dx * (nux - uxx) + dy * (nuy - uyx)) - C.gamma * (h * h * h);
+        sn = d2 > T(0) ? sn * (T(0.35355339059327373) * rsqrt_t(d2)) : sn;
+        bad = bad || (on && x != i && !guessed && sn > C.tol_add);
       }
       const bool accept = !group_any<G>(bad, lane);
-      const bool moved = i == pa || i == pb || i == qa || i == qb;
-      if (accept) {
-        fq = two ? 2 : 1;
-        fpa = pa; fpb = pb; fl1 = lam1;
-        fqa = qa; fqb = qb; fl2 = lam2;
-        run_gi = false;
-        info.iters = two ? 2 : 1;
-      } else if (!two && ok) {
-        // start the loop from u(l) with p active: fixed coordinates carry the
-        // bound multiplier that makes the point stationary
-        seed = true;
-        fpa = pa; fpb = pb; fl1 = lam1; fdx = bdx; fdy = bdy;
-        info.iters = 1;
-        if (moved) {
-          const T cx = i == pa ? T(-2) * bdx : T(2) * bdx;
-          const T cy = i == pa ? T(-2) * bdy : T(2) * bdy;
-          const T vx = uhx - lam1 * cx;
-          const T vy = uhy - lam1 * cy;
-          fx = vx > hix ? 1 : (vx < lox ? -1 : 0);
-          mux = vx > hix ? vx - hix : (vx < lox ? lox - vx : T(0));
-          fy = vy > hiy ? 1 : (vy < loy ? -1 : 0);
-          muy = vy > hiy ? vy - hiy : (vy < loy ? loy - vy : T(0));
-        }
-      } else if (moved && on) {
-        // back to the box clip
-        ux = tclamp(uhx, lox, hix);
-        uy = tclamp(uhy, loy, hiy);
-      }
+      // accepted: the guess is the solution; one rejected row with ok: start
+      // the loop from u(l) with p active; otherwise from u0 (unchanged)
+      const bool seeded = !accept && !two && ok;
+      ux = (accept || seeded) ? nux : ux;
+      uy = (accept || seeded) ? nuy : uy;
+      fq = accept ? (two ? 2 : 1) : fq;
+      seed = seeded;
+      fpa = pa; fpb = pb; fl1 = lam1; fdx = bdx; fdy = bdy;
+      fqa = qa; fqb = qb; fl2 = lam2;
+      run_gi = !accept;
+      info.iters = two ? 2 : 1;
     }
   }
 
