@@ -989,9 +989,10 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, const SimConst<T> &C, int lane, 
         const T cc[4] = {T(-2) * dx, T(-2) * dy, T(2) * dx, T(2) * dy};
         const T un[4] = {__shfl(uhx, la, 64), __shfl(uhy, la, 64), __shfl(uhx, lb, 64),
                          __shfl(uhy, lb, 64)};
-        T lo[4], hi[4];
-        wall_bounds(C, __shfl(px, la, 64), __shfl(py, la, 64), lo[0], hi[0], lo[1], hi[1]);
-        wall_bounds(C, __shfl(px, lb, 64), __shfl(py, lb, 64), lo[2], hi[2], lo[3], hi[3]);
+        const T lo[4] = {__shfl(lox, la, 64), __shfl(loy, la, 64), __shfl(lox, lb, 64),
+                         __shfl(loy, lb, 64)};
+        const T hi[4] = {__shfl(hix, la, 64), __shfl(hiy, la, 64), __shfl(hix, lb, 64),
+                         __shfl(hiy, lb, 64)};
         T e1[4], e2[4];  // multiplier values where coordinate k meets hi_k / lo_k
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
