@@ -89,8 +89,8 @@ __global__ __launch_bounds__(kBlock) void k_env_step(StepArgs<T> A) {
                        : drawn_action(K.get()->key0, K.get()->key1, env_id, A.t_global, i);
   T s, c;
   sincos_t(th, &s, &c);
-  StepOut<T> out = env_step_group<T, G>(A.C, K, &qs[threadIdx.x / G], lane, i, N, on, env_id, action,
-                                        x, y, th, c, s, gx, gy, step, episode,
+  StepOut<T> out = env_step_group<T, G>(K, A.C.qp_cap, &qs[threadIdx.x / G], lane, i, N, on,
+                                        env_id, action, x, y, th, c, s, gx, gy, step, episode,
                                         A.maxviol != nullptr);
   if (on) {
     A.x[r] = x; A.y[r] = y; A.th[r] = th; A.gx[r] = gx; A.gy[r] = gy;
@@ -168,14 +168,15 @@ __global__ __launch_bounds__(kBlock) void k_barrier(BarrierArgs<T> A) {
   const size_t r = (size_t)e * N + (on ? i : 0);
   const T px = A.px[r], py = A.py[r];
   T unx = A.uxn[r], uny = A.uyn[r];
-  preclip(A.C, unx, uny);
+  const ConstRef<T> K = kernarg_const<T>(offsetof(BarrierArgs<T>, C));
+  preclip(*K.get(), unx, uny);
   T lox, hix, loy, hiy;
-  wall_bounds(A.C, px, py, lox, hix, loy, hiy);
+  wall_bounds(*K.get(), px, py, lox, hix, loy, hiy);
   QPScratch<T, G> *sh = &qs[threadIdx.x / G];
   T ux, uy;
   QPActive<T> act;
-  const QPInfo info = qp_solve<T, G>(sh, A.C, lane, i, N, on, px, py, unx, uny, lox, hix, loy,
-                                     hiy, ux, uy, &act);
+  const QPInfo info = qp_solve<T, G>(sh, K, A.C.qp_cap, lane, i, N, on, px, py, unx, uny, lox,
+                                     hix, loy, hiy, ux, uy, &act);
   if (on) { A.ux[r] = ux; A.uy[r] = uy; }
   if (A.lambda) {
     // each lane writes the pairs it owns (i, i+k mod N); active rows come
@@ -198,7 +199,8 @@ __global__ __launch_bounds__(kBlock) void k_barrier(BarrierArgs<T> A) {
     }
   }
   if (A.maxviol) {
-    const T mv = max_violation<T, G>(A.C, lane, i, N, on, px, py, ux, uy, lox, hix, loy, hiy);
+    const T mv = max_violation<T, G>(*K.get(), lane, i, N, on, px, py, ux, uy, lox, hix, loy,
+                                      hiy);
     if (i == 0) A.maxviol[e] = (float)mv;
   }
   if (A.infeasible && i == 0) A.infeasible[e] = info.status == 1 ? 1 : 0;

@@ -36,8 +36,7 @@ __device__ void run_tile(const RunArgs &A, char *wave_lds, int lane, int first, 
   const bool on = i < N;
   const size_t r = (size_t)A.offset[e] + (on ? i : 0);
   const uint32_t env_id = A.env_ids ? A.env_ids[e] : A.env_base + (uint32_t)e;
-  SimConst<float> C = A.C;
-  C.qp_cap = A.qp_iters[N];
+  const int qp_cap = A.qp_iters[N];
   const ConstRef<float> K = kernarg_const<float>(offsetof(RunArgs, C));
 
   float x = 0.f, y = 0.f, th = 0.f, gx = 0.f, gy = 0.f;
@@ -61,8 +60,9 @@ __device__ void run_tile(const RunArgs &A, char *wave_lds, int lane, int first, 
   for (int k = 0; k < nsteps; ++k) {
     const auto *P = K.get();
     const int action = drawn_action(P->key0, P->key1, env_id, (uint32_t)(tb + k), i);
-    const StepOut<float> so = env_step_group<float, G>(C, K, sh, lane, i, N, on, env_id, action, x, y,
-                                                       th, c, s, gx, gy, step, episode, false);
+    const StepOut<float> so = env_step_group<float, G>(K, qp_cap, sh, lane, i, N, on, env_id,
+                                                       action, x, y, th, c, s, gx, gy, step,
+                                                       episode, false);
     rsum += so.reward;
     if (i == 0) {
       if (A.reward_out) A.reward_out[(size_t)k * A.E + e] = so.reward;

@@ -84,8 +84,8 @@ template <> __device__ __forceinline__ double big_v<double>() { return 1.0e300; 
 
 // Per-coordinate bounds: speed box intersected with the wall certificates of
 // the projection point (walls pulled in by r_s / 2, gain c_b gamma, cubic).
-template <typename T>
-__device__ __forceinline__ void wall_bounds(const SimConst<T> &C, T px, T py, T &lox, T &hix,
+template <typename T, typename CS>
+__device__ __forceinline__ void wall_bounds(const CS &C, T px, T py, T &lox, T &hix,
                                             T &loy, T &hiy) {
   const T mxh = C.xwh - px, mxl = px - C.xwl;
   const T myh = C.ywh - py, myl = py - C.ywl;
@@ -854,9 +854,10 @@ __device__ __noinline__ QPLoopOut<T> qp_active_set(QPScratch<T, G> *sh, int lane
 }
 
 template <typename T, int G>
-__device__ QPInfo qp_solve(QPScratch<T, G> *sh, const SimConst<T> &C, int lane, int i, int N,
+__device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int lane, int i, int N,
                            bool on, T px, T py, T uhx, T uhy, T lox, T hix, T loy, T hiy, T &ux,
                            T &uy, QPActive<T> *act_out = nullptr) {
+  const auto &C = *K.get();  // the solver's constants, loaded for this phase
   constexpr int KH = G / 2;
   const T BIG = big_v<T>();
   QPInfo info{0, 0, 0, 0};
@@ -898,7 +899,6 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, const SimConst<T> &C, int lane, 
     else if (uhy < loy) { uy = loy; fy = -1; muy = loy - uhy; }
   }
 
-  const int cap = C.qp_cap > 0 ? C.qp_cap : 8 * N + 32;
   // outcome of the closed-form stages: rows accepted (fq = 1 or 2), or a
   // one-row start for the active-set loop (seed)
   int fq = 0, fpa = -1, fpb = -1, fqa = -1, fqb = -1;
@@ -1115,7 +1115,7 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, const SimConst<T> &C, int lane, 
     const QPLoopOut<T> r = qp_active_set<T, G>(sh, lane, i, N, on, px, py, uhx, uhy, lox, hix,
                                                loy, hiy, seed, fpa, fpb, fl1, fdx, fdy, C.rs2,
                                                C.gamma, C.vmax4, C.tol_add, C.eps_z, C.eps_r,
-                                               C.qp_cap);
+                                               qp_cap);
     ux = r.ux;
     uy = r.uy;
     info.status = r.status;

@@ -309,9 +309,9 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
 
     // ---- 4. env step --------------------------------------------------------
     if (env_ok) {
-      const StepOut<float> so = env_step_group<float, G>(A.C, K, sh, lane, i, N, on, env_id, action,
-                                                         x, y, th, c, s, gx, gy, step, episode,
-                                                         false);
+      const StepOut<float> so = env_step_group<float, G>(K, A.C.qp_cap, sh, lane, i, N, on, env_id,
+                                                         action, x, y, th, c, s, gx, gy, step,
+                                                         episode, false);
       if (i == 0) {
         (A.reward + (size_t)t * A.E)[(uint32_t)e] = so.reward;
         (A.done + (size_t)t * A.E)[(uint32_t)e] = so.done ? 1 : 0;

@@ -20,8 +20,8 @@ __device__ __forceinline__ int drawn_action(uint32_t k0, uint32_t k1, uint32_t e
 }
 
 // Magnitude limit of the nominal command.
-template <typename T>
-__device__ __forceinline__ void preclip(const SimConst<T> &C, T &ux, T &uy) {
+template <typename T, typename CS>
+__device__ __forceinline__ void preclip(const CS &C, T &ux, T &uy) {
   const T nrm = sqrt_t(ux * ux + uy * uy);
   if (nrm > C.vmax) {
     const T sc = C.vmax / nrm;
@@ -32,8 +32,8 @@ __device__ __forceinline__ void preclip(const SimConst<T> &C, T &ux, T &uy) {
 
 // Single-integrator command at the projection point -> unicycle (v, w), then
 // GRITSBot wheel-speed saturation.
-template <typename T>
-__device__ __forceinline__ void si_to_uni(const SimConst<T> &C, T c, T s, T ux, T uy, T &v, T &w) {
+template <typename T, typename CS>
+__device__ __forceinline__ void si_to_uni(const CS &C, T c, T s, T ux, T uy, T &v, T &w) {
   v = c * ux + s * uy;
   w = (c * uy - s * ux) * C.inv_l;
   if (C.R > T(0)) {
@@ -48,8 +48,8 @@ __device__ __forceinline__ void si_to_uni(const SimConst<T> &C, T c, T s, T ux, 
 
 // Explicit Euler with the pre-step heading; heading wrapped to [-pi, pi]
 // (|dt w| < pi, so one correction suffices).
-template <typename T>
-__device__ __forceinline__ void integrate(const SimConst<T> &C, T c, T s, T v, T w, T &x, T &y,
+template <typename T, typename CS>
+__device__ __forceinline__ void integrate(const CS &C, T c, T s, T v, T w, T &x, T &y,
                                           T &th) {
   x += C.dt * v * c;
   y += C.dt * v * s;
@@ -149,8 +149,8 @@ __device__ __forceinline__ void write_obs(T *o, int lane, int i, int N, bool on,
 
 // Largest normalised violation of (ux, uy) against the rows (owner scan) and
 // bounds; group-uniform result.
-template <typename T, int G>
-__device__ T max_violation(const SimConst<T> &C, int lane, int i, int N, bool on, T px, T py,
+template <typename T, int G, typename CS>
+__device__ T max_violation(const CS &C, int lane, int i, int N, bool on, T px, T py,
                            T ux, T uy, T lox, T hix, T loy, T hiy) {
   const int base = lane & ~(G - 1);
   T worst = T(0);
@@ -185,12 +185,15 @@ template <typename T> struct StepOut {
 // are group-uniform and updated. Observation of the post-step state is left
 // to the caller (c, s are refreshed).
 template <typename T, int G>
-__device__ StepOut<T> env_step_group(const SimConst<T> &C, ConstRef<T> K, QPScratch<T, G> *sh,
-                                     int lane, int i, int N, bool on, uint32_t env_id, int action, T &x, T &y,
+__device__ StepOut<T> env_step_group(ConstRef<T> K, int qp_cap, QPScratch<T, G> *sh, int lane,
+                                     int i, int N, bool on, uint32_t env_id, int action, T &x, T &y,
                                      T &th, T &c, T &s, T &gx, T &gy, int &step, int &episode,
                                      bool want_viol) {
   StepOut<T> out;
+  // Constants are read from the kernel arguments phase by phase (see
+  // ConstRef), so that they do not hold scalar registers across the step.
   // projection point and nominal command
+  const auto &C = *K.get();
   const T px = x + C.l * c, py = y + C.l * s;
   T unx, uny;
   if (C.controller == 1) {
@@ -204,14 +207,16 @@ __device__ StepOut<T> env_step_group(const SimConst<T> &C, ConstRef<T> K, QPScra
   }
   preclip(C, unx, uny);
   T lox, hix, loy, hiy;
-  wall_bounds(C, px, py, lox, hix, loy, hiy);
+  wall_bounds(*K.get(), px, py, lox, hix, loy, hiy);
   T ux, uy;
-  out.qp = qp_solve<T, G>(sh, C, lane, i, N, on, px, py, unx, uny, lox, hix, loy, hiy, ux, uy);
-  out.maxviol = want_viol ? max_violation<T, G>(C, lane, i, N, on, px, py, ux, uy, lox, hix, loy, hiy)
+  out.qp = qp_solve<T, G>(sh, K, qp_cap, lane, i, N, on, px, py, unx, uny, lox, hix, loy, hiy, ux,
+                          uy);
+  out.maxviol = want_viol ? max_violation<T, G>(*K.get(), lane, i, N, on, px, py, ux, uy, lox, hix,
+                                                loy, hiy)
                           : T(0);
   T v, w;
-  si_to_uni(C, c, s, ux, uy, v, w);
-  if (on) integrate(C, c, s, v, w, x, y, th);
+  si_to_uni(*K.get(), c, s, ux, uy, v, w);
+  if (on) integrate(*K.get(), c, s, v, w, x, y, th);
   // reward and termination
   step += 1;
   T dist = T(0);
@@ -220,8 +225,9 @@ __device__ StepOut<T> env_step_group(const SimConst<T> &C, ConstRef<T> K, QPScra
     dist = sqrt_t(ex * ex + ey * ey);
   }
   out.reward = -gsum<G>(dist);
-  const bool near_all = group_all<G>(!on || dist < C.goal_r, lane);
-  out.done = (C.goal_r > T(0) && near_all) || (C.max_steps > 0 && step >= C.max_steps);
+  const auto &Cd = *K.get();
+  const bool near_all = group_all<G>(!on || dist < Cd.goal_r, lane);
+  out.done = (Cd.goal_r > T(0) && near_all) || (Cd.max_steps > 0 && step >= Cd.max_steps);
   if (out.done) {
     episode += 1;
     step = 0;
