@@ -5,8 +5,9 @@
 // each wavefront owns 64/G environments (lane i of a G-lane group = robot i).
 // Per step and wavefront:
 //   1. observation rows (2N+4 floats) are built in registers and staged in LDS
-//      packed env after env, then copied to HBM with 16-byte vector stores
-//      that cover one contiguous range per wavefront;
+//      packed env after env for the MLP; with a compile-time robot count each
+//      lane stores its own row to HBM with 16-byte stores, otherwise the
+//      staging area is copied out as one contiguous range per wavefront;
 //   2. the policy runs transposed on v_mfma_f32_16x16x32_bf16: for each tile
 //      of 16 robots, H1^T = W1^T X^T (K = 32 features), H2^T = W2^T H1^T,
 //      logits^T = W3^T H2^T (K = 64 in two steps). The K order of layers 2-3
@@ -178,28 +179,60 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
   uint4 qblk = make_uint4(0u, 0u, 0u, 0u);  // this lane's Philox block (G >= 4)
   for (int t = 0; t < A.H; ++t) {
     // ---- 1. observation -> LDS (packed) -> HBM --------------------------
-    float *o = obs_w + row * D;
-    if (on) { o[0] = x; o[1] = y; o[2] = c; o[3] = s; }
-    static_for<1, G>([&](auto kc) {  // neighbour (i + K) mod G by DPP rotation
-      constexpr int K = decltype(kc)::value;
-      const float xj = grot<G, K>(x, lane), yj = grot<G, K>(y, lane);
-      const int j = (i + K) & (G - 1);
-      if (on && j < N) {
-        const int m = 4 + 2 * (j < i ? j : j - 1);
-        o[m] = xj - x;
-        o[m + 1] = yj - y;
+    if constexpr (NC > 0 && ((2 * NC + 4) & 3) == 0) {
+      // Row assembled in registers: slot s of the neighbour block holds robot
+      // j = s + (s >= i), fetched by LDS permute. The row goes to the MLP's
+      // LDS staging and to HBM as 16-byte stores.
+      constexpr int DC = 2 * NC + 4;
+      float rw[DC];
+      rw[0] = x; rw[1] = y; rw[2] = c; rw[3] = s;
+      const int gl4 = (lane & ~(G - 1)) << 2;
+      static_for<0, NC - 1>([&](auto sc) {
+        constexpr int S = decltype(sc)::value;
+        const int src = gl4 + ((S + (S >= i ? 1 : 0)) << 2);
+        rw[4 + 2 * S] = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(src, __builtin_bit_cast(int, x))) - x;
+        rw[5 + 2 * S] = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(src, __builtin_bit_cast(int, y))) - y;
+      });
+      rw[DC - 2] = gx - x;
+      rw[DC - 1] = gy - y;
+      if (on) {
+        float4 *o4 = reinterpret_cast<float4 *>(obs_w + row * DC);
+#pragma unroll
+        for (int q = 0; q < DC / 4; ++q)
+          o4[q] = make_float4(rw[4 * q], rw[4 * q + 1], rw[4 * q + 2], rw[4 * q + 3]);
+        if (A.obs) {
+          float4 *g4 = reinterpret_cast<float4 *>(A.obs + ((size_t)t * A.E + e0) * (size_t)(NC * DC)) +
+                       row * (DC / 4);
+#pragma unroll
+          for (int q = 0; q < DC / 4; ++q)
+            g4[q] = make_float4(rw[4 * q], rw[4 * q + 1], rw[4 * q + 2], rw[4 * q + 3]);
+        }
       }
-    });
-    if (on) { o[D - 2] = gx - x; o[D - 1] = gy - y; }
-    wave_lds_sync();
-    if (A.obs) {
-      float *dst = A.obs + ((size_t)t * A.E + e0) * (size_t)(N * D);  // wavefront-uniform
-      if (vec4) {
-        for (int q = lane; q < (nfl >> 2); q += 64)
-          reinterpret_cast<float4 *>(dst)[q] = reinterpret_cast<const float4 *>(obs_w)[q];
-      } else {
-        for (int q = lane; q < (nfl >> 1); q += 64)
-          reinterpret_cast<float2 *>(dst)[q] = reinterpret_cast<const float2 *>(obs_w)[q];
+      wave_lds_sync();
+    } else {
+      float *o = obs_w + row * D;
+      if (on) { o[0] = x; o[1] = y; o[2] = c; o[3] = s; }
+      static_for<1, G>([&](auto kc) {  // neighbour (i + K) mod G by rotation
+        constexpr int K = decltype(kc)::value;
+        const float xj = grot<G, K>(x, lane), yj = grot<G, K>(y, lane);
+        const int j = (i + K) & (G - 1);
+        if (on && j < N) {
+          const int m = 4 + 2 * (j < i ? j : j - 1);
+          o[m] = xj - x;
+          o[m + 1] = yj - y;
+        }
+      });
+      if (on) { o[D - 2] = gx - x; o[D - 1] = gy - y; }
+      wave_lds_sync();
+      if (A.obs) {
+        float *dst = A.obs + ((size_t)t * A.E + e0) * (size_t)(N * D);  // wavefront-uniform
+        if (vec4) {
+          for (int q = lane; q < (nfl >> 2); q += 64)
+            reinterpret_cast<float4 *>(dst)[q] = reinterpret_cast<const float4 *>(obs_w)[q];
+        } else {
+          for (int q = lane; q < (nfl >> 1); q += 64)
+            reinterpret_cast<float2 *>(dst)[q] = reinterpret_cast<const float2 *>(obs_w)[q];
+        }
       }
     }
 
