@@ -191,6 +191,26 @@ rs_status rollout(rs_ctx *ctx, const rs_params *p, const rs_batch *b, const rs_p
                   float *reward, uint8_t *done, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Snapshot / restore (checkpoint and resume) of a batch's state: pose, goal,
+ * step and episode arrays. The stream is counter based (env id, stream time),
+ * so these are all a bit-identical resume needs. A snapshot is a host buffer
+ * of rs_snapshot_bytes bytes: a 32-byte header (magic "RSSNAP1", dtype,
+ * num_envs, robots_total), then x, y, theta, goal_x, goal_y ([robots_total]
+ * values of dtype each) and step, episode ([num_envs] int32 each).
+ * robots_total = num_envs * robots for a uniform batch, or
+ * rs_plan_total_robots for a mixed one. Both calls are stream-ordered and
+ * synchronise `stream` before returning. Errors: NULL pointers, a buffer
+ * smaller than rs_snapshot_bytes, or (restore) a header that does not match
+ * dtype / num_envs / robots_total: RS_ERR_INVALID_ARG before any copy;
+ * copy failures: RS_ERR_DEVICE.
+ * ------------------------------------------------------------------------- */
+int64_t rs_snapshot_bytes(int32_t dtype, int32_t num_envs, int64_t robots_total);
+rs_status rs_snapshot(rs_ctx *ctx, int32_t dtype, const rs_batch *b, int64_t robots_total,
+                      void *host, int64_t bytes, void *stream);
+rs_status rs_restore(rs_ctx *ctx, int32_t dtype, const rs_batch *b, int64_t robots_total,
+                     const void *host, int64_t bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Mixed-size batches (environments with different robot counts in one launch).
  * A plan holds the schedule: envs grouped by robot count into wavefront tiles
  * (envs per wavefront chosen per robot count by the autotuner or `schedule`).

@@ -124,6 +124,9 @@ def lib():
         "rs_server_tick": (i32, [_VP, P(i32)]),
         "rs_server_poll": (i32, [_VP, P(RsRequestInfo), _VP, _VP]),
         "rs_server_stats_get": (i32, [_VP, P(RsServerStats)]),
+        "rs_snapshot_bytes": (i64, [i32, i32, i64]),
+        "rs_snapshot": (i32, [_VP, i32, P(RsBatch), i64, _VP, i64, _VP]),
+        "rs_restore": (i32, [_VP, i32, P(RsBatch), i64, _VP, i64, _VP]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name, None)
@@ -295,6 +298,37 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def _batch_dtype(b: Batch) -> int:
+    import torch
+
+    return RS_F64 if b.x.dtype == torch.float64 else RS_F32
+
+
+def snapshot(ctx: Context, b: Batch, stream=None):
+    """Host copy of the batch's state (pose, goal, step, episode) as a numpy
+    uint8 buffer in the rs_snapshot layout."""
+    import numpy as np
+
+    dtype = _batch_dtype(b)
+    robots_total = int(b.x.numel())
+    n = lib().rs_snapshot_bytes(dtype, b.num_envs, robots_total)
+    buf = np.zeros(n, np.uint8)
+    cb = b.c()
+    _check(lib().rs_snapshot(ctx.handle, dtype, ctypes.byref(cb), robots_total,
+                             buf.ctypes.data, n, _stream(stream)))
+    return buf
+
+
+def restore(ctx: Context, b: Batch, buf, stream=None):
+    """Write a snapshot buffer back into the batch (same shape and precision)."""
+    import numpy as np
+
+    buf = np.ascontiguousarray(buf, dtype=np.uint8)
+    cb = b.c()
+    _check(lib().rs_restore(ctx.handle, _batch_dtype(b), ctypes.byref(cb), int(b.x.numel()),
+                            buf.ctypes.data, buf.size, _stream(stream)))
 
 
 def env_reset_mixed(ctx: Context, p: RsParams, plan: Plan, b: Batch, mask=None, stream=None):

@@ -127,3 +127,30 @@ def test_gpu_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(robostep, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="missing"):
         robostep.lib()
+
+
+def test_snapshot_size_and_argument_checks(R):
+    """Snapshot layout size, and restore refuses a buffer whose header does not
+    match the batch before any device copy."""
+    import numpy as np
+
+    L = R.lib()
+    assert L.rs_snapshot_bytes(R.RS_F32, 10, 40) == 32 + 5 * 40 * 4 + 2 * 10 * 4
+    assert L.rs_snapshot_bytes(R.RS_F64, 10, 40) == 32 + 5 * 40 * 8 + 2 * 10 * 4
+    fake = ctypes.c_void_p(0x1000)
+    b = R.RsBatch(10, 4, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 0)
+    n = L.rs_snapshot_bytes(R.RS_F32, 10, 40)
+    buf = np.zeros(n, np.uint8)
+    # not a snapshot: wrong magic
+    assert L.rs_restore(fake, R.RS_F32, ctypes.byref(b), 40, buf.ctypes.data, n, None) == 1
+    assert b"not a snapshot" in L.rs_last_error()
+    # right magic, wrong shape
+    buf[:8] = np.frombuffer(b"RSSNAP1\0", np.uint8)
+    buf[8:12] = np.frombuffer(np.int32(0).tobytes(), np.uint8)
+    buf[12:16] = np.frombuffer(np.int32(11).tobytes(), np.uint8)
+    buf[16:24] = np.frombuffer(np.int64(40).tobytes(), np.uint8)
+    assert L.rs_restore(fake, R.RS_F32, ctypes.byref(b), 40, buf.ctypes.data, n, None) == 1
+    assert b"does not match" in L.rs_last_error()
+    # buffer too small
+    assert L.rs_snapshot(fake, R.RS_F32, ctypes.byref(b), 40, buf.ctypes.data, n - 1, None) == 1
+    assert L.rs_snapshot(None, R.RS_F32, ctypes.byref(b), 40, buf.ctypes.data, n, None) == 1
