@@ -464,6 +464,19 @@ template <int G, typename T> __device__ __forceinline__ void gargmin(T &v, int &
   if constexpr (G >= 16) step(std::integral_constant<int, 0x140>{});
 }
 
+// Lane of the group holding the largest positive score (ties: smaller lane),
+// or -1 if no lane has one. A non-negative float orders like its bit pattern
+// read as an unsigned integer, so the score's bits, truncated by one byte,
+// carry 255 - lane in the low byte and a single unsigned-max butterfly
+// decides; the caller then reads the winner's payload from its lane.
+template <int G, typename T>
+__device__ __forceinline__ int group_argmax_lane(T score, bool has, int i) {
+  const uint32_t key0 =
+      has ? ((__float_as_uint((float)score) & 0xFFFFFF00u) | (uint32_t)(255 - i)) : 0u;
+  const int key = gred<G>((int)key0, [](int a, int b) { return (uint32_t)a > (uint32_t)b ? a : b; });
+  return key == 0 ? -1 : 255 - (key & 255);
+}
+
 // Owner lane and rotation of pair (a, b), a < b, under the mod-G ownership.
 template <int G> __device__ __forceinline__ void pair_owner_g(int a, int b, int &owner, int &k) {
   const int d = b - a;
@@ -862,13 +875,23 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
   const T BIG = big_v<T>();
   QPInfo info{0, 0, 0, 0};
 
-  // --- geometry of the owned pairs ------------------------------------------
-  T cdx[KH], cdy[KH], cb[KH], crn[KH];
+  // --- box clip u0 (every bound holds there) ---------------------------------
+  ux = uhx;
+  uy = uhy;
+  if (on) {
+    ux = uhx > hix ? hix : (uhx < lox ? lox : uhx);
+    uy = uhy > hiy ? hiy : (uhy < loy ? loy : uhy);
+  }
+
+  // --- geometry of the owned pairs and their violations at u0 ---------------
+  // (the partner's position and command are fetched together)
+  T cdx[KH], cdy[KH], cb[KH], crn[KH], snk[KH];
   int cpid[KH];
   bool coincide = false;
   static_for<1, KH + 1>([&](auto kc) {
     constexpr int K = decltype(kc)::value;
     const T pxj = grot<G, K>(px, lane), pyj = grot<G, K>(py, lane);
+    const T uxj = grot<G, K>(ux, lane), uyj = grot<G, K>(uy, lane);
     const int j = (i + K) & (G - 1);
     const bool valid = on && j < N && !(2 * K == G && i >= KH);
     const bool ia = i < j;
@@ -884,20 +907,12 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
     crn[K - 1] = d2 > T(0) ? T(0.35355339059327373) * rsqrt_t(d2) : T(0);
     cpid[K - 1] = (cand && d2 > T(0)) ? ((ia ? i : j) << 4 | (ia ? j : i)) : -1;
     if (cand && !(d2 > T(0)) && bb < T(0)) coincide = true;
+    const T dux = ia ? uxj - ux : ux - uxj;
+    const T duy = ia ? uyj - uy : uy - uyj;
+    const T sn = (T(2) * (dx * dux + dy * duy) - bb) * crn[K - 1];
+    snk[K - 1] = cpid[K - 1] >= 0 ? sn : -BIG;
   });
   bool dead = group_any<G>(coincide || (on && (lox > hix || loy > hiy)), lane);
-
-  // --- start: clip to the box; active bounds fix their coordinate ----------
-  int fx = 0, fy = 0;
-  T mux = T(0), muy = T(0);
-  ux = uhx;
-  uy = uhy;
-  if (on) {
-    if (uhx > hix) { ux = hix; fx = 1; mux = uhx - hix; }
-    else if (uhx < lox) { ux = lox; fx = -1; mux = lox - uhx; }
-    if (uhy > hiy) { uy = hiy; fy = 1; muy = uhy - hiy; }
-    else if (uhy < loy) { uy = loy; fy = -1; muy = loy - uhy; }
-  }
 
   // outcome of the closed-form stages: rows accepted (fq = 1 or 2), or a
   // one-row start for the active-set loop (seed)
@@ -927,30 +942,32 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
   if (!dead) {
     T best = C.tol_add, bdx = T(0), bdy = T(0), bbb = T(0);
     int bid = -1, nviol = 0;
-    T snk[KH];
     static_for<1, KH + 1>([&](auto kc) {
       constexpr int K = decltype(kc)::value;
-      const T uxj = grot<G, K>(ux, lane), uyj = grot<G, K>(uy, lane);
-      const bool ia = i < ((i + K) & (G - 1));
-      const T dux = ia ? uxj - ux : ux - uxj;
-      const T duy = ia ? uyj - uy : uy - uyj;
-      const T sn = (T(2) * (cdx[K - 1] * dux + cdy[K - 1] * duy) - cb[K - 1]) * crn[K - 1];
-      snk[K - 1] = cpid[K - 1] >= 0 ? sn : -BIG;
       nviol += snk[K - 1] > C.tol_add ? 1 : 0;
       if (snk[K - 1] > best) {
-        best = sn;
+        best = snk[K - 1];
         bid = cpid[K - 1];
         bdx = cdx[K - 1];
         bdy = cdy[K - 1];
         bbb = cb[K - 1];
       }
     });
-    gargmax_payload<G>(best, bid, bdx, bdy, bbb);
+    // most violated row of the group: winner lane by one integer butterfly,
+    // its row's data read from that lane
+    const int gbase = lane & ~(G - 1);
+    const int wl = group_argmax_lane<G>(best, bid >= 0, i);
     const int nv = gsum<G>(nviol);
+    {
+      const int src = gbase + (wl < 0 ? 0 : wl);
+      bid = wl < 0 ? -1 : __shfl(bid, src, 64);
+      bdx = __shfl(bdx, src, 64);
+      bdy = __shfl(bdy, src, 64);
+      bbb = __shfl(bbb, src, 64);
+    }
     if (bid < 0) {
       run_gi = false;  // u0 is the solution
     } else if (nv <= 2) {
-      const int gbase = lane & ~(G - 1);
       // the other violated row, if any
       T b2 = C.tol_add, e2x = T(0), e2y = T(0), beta2 = T(0);
       int id2 = -1;
@@ -965,7 +982,12 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
             beta2 = cb[K - 1];
           }
         });
-        gargmax_payload<G>(b2, id2, e2x, e2y, beta2);
+        const int w2 = group_argmax_lane<G>(b2, id2 >= 0, i);
+        const int src = gbase + (w2 < 0 ? 0 : w2);
+        id2 = w2 < 0 ? -1 : __shfl(id2, src, 64);
+        e2x = __shfl(e2x, src, 64);
+        e2y = __shfl(e2y, src, 64);
+        beta2 = __shfl(beta2, src, 64);
       }
       const bool two = nv == 2 && id2 >= 0;
       const int pa = bid >> 4, pb = bid & 15;
@@ -1079,11 +1101,14 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
         const bool out = mv && (vx < lox || vx > hix || vy < loy || vy > hiy);
         ok = ok && !group_any<G>(out, lane);
       }
-      // check every row through a moved robot, except the guessed ones
+      // check every row through a moved robot, except the guessed ones (the
+      // second row's robots only when some group of the wavefront has one)
       const int mr[4] = {pa, pb, qa, qb};
+      const bool any_two = __ballot(two) != 0;
       bool bad = !ok;
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
+        if (m >= 2 && !any_two) break;
         const int x = mr[m], lx = gbase + x;
         const T pxx = __shfl(px, lx, 64), pyx = __shfl(py, lx, 64);
         const T uxx = __shfl(nux, lx, 64), uyx = __shfl(nuy, lx, 64);
