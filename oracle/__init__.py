@@ -46,6 +46,8 @@ class OrcParams(ctypes.Structure):
         ("min_sep", ctypes.c_double), ("grid", ctypes.c_double),
         ("max_steps", ctypes.c_int32), ("controller", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
+        ("waypoint_step", ctypes.c_double), ("pos_gain", ctypes.c_double),
+        ("ang_gain", ctypes.c_double), ("action_noise", ctypes.c_double),
     ]
 
 
@@ -74,6 +76,10 @@ class Params:
     max_steps: int = 500
     controller: int = 0
     seed: int = 0
+    waypoint_step: float = 0.2
+    pos_gain: float = 0.8
+    ang_gain: float = math.pi / 2
+    action_noise: float = 0.0
 
     def c(self) -> OrcParams:
         return OrcParams(**{f.name: getattr(self, f.name) for f in fields(self)})
@@ -111,6 +117,13 @@ def lib():
         L.orc_max_violation.restype = ctypes.c_double
         L.orc_si_to_uni.argtypes = [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                     _D, _D]
+        L.orc_unicycle_position.argtypes = [_P] + [ctypes.c_double] * 5 + [_D, _D]
+        L.orc_uni_to_si.argtypes = [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double, _D,
+                                    _D]
+        L.orc_action_noise.argtypes = [_P, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32, _D,
+                                       _D]
+        L.orc_nominal_command.argtypes = [_P, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64,
+                                          _D, _D, _D, _D, _D, _U8, _U8, _D, _D]
         L.orc_observe.argtypes = [ctypes.c_int32, _D, _D, _D, _D, _D, _D]
         L.orc_env_step.argtypes = [_P, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64,
                                    _D, _D, _D, _D, _D, _I32, _I32, _U8, _U8, _D, _D, _U8,
@@ -218,6 +231,43 @@ def si_to_uni(p: Params, theta: float, ux: float, uy: float):
     cp = p.c()
     lib().orc_si_to_uni(ctypes.byref(cp), theta, ux, uy, ctypes.byref(v), ctypes.byref(w))
     return v.value, w.value
+
+
+def unicycle_position(p: Params, x: float, y: float, theta: float, wx: float, wy: float):
+    v, w = ctypes.c_double(), ctypes.c_double()
+    cp = p.c()
+    lib().orc_unicycle_position(ctypes.byref(cp), x, y, theta, wx, wy, ctypes.byref(v),
+                                ctypes.byref(w))
+    return v.value, w.value
+
+
+def uni_to_si(p: Params, theta: float, v: float, w: float):
+    ux, uy = ctypes.c_double(), ctypes.c_double()
+    cp = p.c()
+    lib().orc_uni_to_si(ctypes.byref(cp), theta, v, w, ctypes.byref(ux), ctypes.byref(uy))
+    return ux.value, uy.value
+
+
+def action_noise(p: Params, env_id: int, t_global: int, i: int):
+    nx, ny = ctypes.c_double(), ctypes.c_double()
+    cp = p.c()
+    lib().orc_action_noise(ctypes.byref(cp), env_id, t_global, i, ctypes.byref(nx),
+                           ctypes.byref(ny))
+    return nx.value, ny.value
+
+
+def nominal_command(p: Params, state: dict, env_id: int, t_global: int, actions=None):
+    """Nominal command (before the magnitude pre-clip) of every robot of one
+    env; returns (unx, uny, actions used)."""
+    n = state["x"].size
+    act = None if actions is None else np.ascontiguousarray(actions, dtype=np.uint8)
+    used = np.zeros(n, np.uint8)
+    unx, uny = np.zeros(n), np.zeros(n)
+    cp = p.c()
+    lib().orc_nominal_command(ctypes.byref(cp), n, env_id, t_global,
+                              *[_ptr(_f64(state[k]), _D) for k in ("x", "y", "th", "gx", "gy")],
+                              _ptr(act, _U8), _ptr(used, _U8), _ptr(unx, _D), _ptr(uny, _D))
+    return unx, uny, (used if act is None else act)
 
 
 def observe(x, y, th, gx, gy):

@@ -7,7 +7,7 @@
  *                          unicycle controllers, barrier-certificate QP.
  *   Appendix, Navigation   observation = own position + vector to goal,
  *                          reward = -1 x distance of robots to their goals.
- *   Sec. 8 "Limitations"   the simulator's QP solver differs from the testbed's;
+ *   Sec. 9 "Limitations"   the simulator's QP solver differs from the testbed's;
  *                          the ground truth here is the exact minimiser.
  * The paper states none of the formulas; the readings used are stated on each
  * function below.
@@ -30,7 +30,7 @@
 
 /* Stream purposes (word 2 of the counter carries purpose << 24 | index). */
 enum { PURPOSE_ACTION = 0, PURPOSE_POLICY = 1, PURPOSE_POSE = 2, PURPOSE_GOAL = 3,
-       PURPOSE_HEADING = 4 };
+       PURPOSE_HEADING = 4, PURPOSE_WEIGHTS = 5, PURPOSE_NOISE = 6 };
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10, as published by Salmon et al. (SC'11): ten rounds of two   */
@@ -500,6 +500,90 @@ void orc_observe(int32_t n, const double *x, const double *y, const double *th, 
 }
 
 /* ------------------------------------------------------------------------ */
+/* Waypoint actions (Sec. 6.1: a controller manager turns waypoint actions  */
+/* into unicycle commands, then the barrier filters them; Appendix B: every  */
+/* scenario trains on waypoints followed by a unicycle position controller). */
+/* Readings: a move action a sets the waypoint waypoint_step ahead of the    */
+/* robot's centre in direction dir(a), afresh at every step; the controller  */
+/* is the classic turn-and-go law on the distance rho and the bearing alpha  */
+/* of the waypoint relative to the heading,                                  */
+/*   v = k_v rho cos(alpha),  w = k_w sin(alpha),                             */
+/* idle (0, 0) at the waypoint; its unicycle command enters the barrier as   */
+/* the velocity of the projection point.                                     */
+/* ------------------------------------------------------------------------ */
+void orc_unicycle_position(const orc_params *p, double x, double y, double theta, double wx,
+                           double wy, double *v, double *w) {
+  double ex = wx - x, ey = wy - y;
+  double rho = sqrt(ex * ex + ey * ey);
+  if (rho == 0.0) {
+    *v = 0.0;
+    *w = 0.0;
+    return;
+  }
+  double alpha = atan2(ey, ex) - theta;
+  *v = p->pos_gain * rho * cos(alpha);
+  *w = p->ang_gain * sin(alpha);
+}
+
+/* The projection point sits l ahead of the axle: its velocity is the
+ * centre's velocity v (cos th, sin th) plus l w (-sin th, cos th). */
+void orc_uni_to_si(const orc_params *p, double theta, double v, double w, double *ux,
+                   double *uy) {
+  double c = cos(theta), s = sin(theta), l = p->proj_dist;
+  *ux = v * c - l * w * s;
+  *uy = v * s + l * w * c;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Action noise (Sec. 7, domain randomisation: the policy trained with      */
+/* action noise narrows the sim-to-real gap; the paper gives no             */
+/* distribution). Reading: each coordinate of the nominal command gets an   */
+/* independent uniform draw in [-sigma, sigma) from stream purpose 6,       */
+/* counter (env_id, t, 6 << 24 | i, 0), words 0 (x) and 1 (y).              */
+/* ------------------------------------------------------------------------ */
+void orc_action_noise(const orc_params *p, uint64_t env_id, int64_t t_global, int32_t i,
+                      double *nx, double *ny) {
+  uint32_t o[4];
+  stream_block(p, (uint32_t)env_id, (uint32_t)t_global, PURPOSE_NOISE, (uint32_t)i, 0, o);
+  *nx = p->action_noise * (2.0 * unit_uniform(o[0]) - 1.0);
+  *ny = p->action_noise * (2.0 * unit_uniform(o[1]) - 1.0);
+}
+
+void orc_nominal_command(const orc_params *p, int32_t n, uint64_t env_id, int64_t t_global,
+                         const double *x, const double *y, const double *th, const double *gx,
+                         const double *gy, const uint8_t *actions, uint8_t *actions_used,
+                         double *unx, double *uny) {
+  for (int32_t i = 0; i < n; ++i) {
+    if (p->controller == 1) {
+      double px = x[i] + p->proj_dist * cos(th[i]);
+      double py = y[i] + p->proj_dist * sin(th[i]);
+      unx[i] = p->kp * (gx[i] - px);
+      uny[i] = p->kp * (gy[i] - py);
+    } else {
+      int32_t a = actions ? (int32_t)actions[i] : orc_random_action(p, env_id, t_global, i);
+      if (actions_used) actions_used[i] = (uint8_t)a;
+      double dx, dy;
+      move_direction(a, &dx, &dy);
+      if (p->controller == 2) {
+        double wx = x[i] + p->waypoint_step * dx, wy = y[i] + p->waypoint_step * dy;
+        double v, w;
+        orc_unicycle_position(p, x[i], y[i], th[i], wx, wy, &v, &w);
+        orc_uni_to_si(p, th[i], v, w, &unx[i], &uny[i]);
+      } else {
+        unx[i] = p->action_speed * dx;
+        uny[i] = p->action_speed * dy;
+      }
+    }
+    if (p->action_noise > 0.0) {
+      double nx, ny;
+      orc_action_noise(p, env_id, t_global, i, &nx, &ny);
+      unx[i] += nx;
+      uny[i] += ny;
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
 /* One environment step.                                                     */
 /* ------------------------------------------------------------------------ */
 int32_t orc_env_step(const orc_params *p, int32_t n, uint64_t env_id, int64_t t_global,
@@ -513,19 +597,7 @@ int32_t orc_env_step(const orc_params *p, int32_t n, uint64_t env_id, int64_t t_
     px[i] = x[i] + p->proj_dist * cos(th[i]);
     py[i] = y[i] + p->proj_dist * sin(th[i]);
   }
-  for (int32_t i = 0; i < n; ++i) {
-    if (p->controller == 1) {
-      unx[i] = p->kp * (gx[i] - px[i]);
-      uny[i] = p->kp * (gy[i] - py[i]);
-    } else {
-      int32_t a = actions ? (int32_t)actions[i] : orc_random_action(p, env_id, t_global, i);
-      if (actions_used) actions_used[i] = (uint8_t)a;
-      double dx, dy;
-      move_direction(a, &dx, &dy);
-      unx[i] = p->action_speed * dx;
-      uny[i] = p->action_speed * dy;
-    }
-  }
+  orc_nominal_command(p, n, env_id, t_global, x, y, th, gx, gy, actions, actions_used, unx, uny);
   double mv = 0.0;
   int32_t status = orc_barrier_certificate(p, n, px, py, unx, uny, ux, uy, NULL, NULL, &mv);
   if (infeasible) *infeasible = (uint8_t)(status == 1);

@@ -42,8 +42,13 @@ typedef struct {
   double min_sep;            /* reset sampler minimum separation */
   double grid;               /* reset sampler lattice pitch */
   int32_t max_steps;         /* <= 0 disables the time limit */
-  int32_t controller;        /* 0: discrete moves, 1: proportional go-to-goal */
+  int32_t controller;        /* 0: discrete moves, 1: proportional go-to-goal,
+                                2: waypoints followed by a unicycle position controller */
   uint64_t seed;             /* Philox key */
+  double waypoint_step;      /* controller 2: distance of the waypoint a move action sets */
+  double pos_gain;           /* controller 2: k_v, linear speed per metre of distance */
+  double ang_gain;           /* controller 2: k_w, turn rate at a 90-degree bearing */
+  double action_noise;       /* sigma of the uniform action noise; 0 disables it */
 } orc_params;
 
 /* Philox4x32-10 block cipher (Salmon, Moraes, Dror, Shaw, SC'11). */
@@ -82,6 +87,29 @@ int32_t orc_barrier_certificate(const orc_params *p, int32_t n, const double *px
 /* Largest normalized violation of u against the rows and bounds at (px, py). */
 double orc_max_violation(const orc_params *p, int32_t n, const double *px, const double *py,
                          const double *ux, const double *uy);
+
+/* Unicycle position controller: (v, w) that drive a robot at (x, y, theta)
+ * toward the waypoint (wx, wy). */
+void orc_unicycle_position(const orc_params *p, double x, double y, double theta, double wx,
+                           double wy, double *v, double *w);
+
+/* Unicycle command (v, w) -> velocity of the projection point. */
+void orc_uni_to_si(const orc_params *p, double theta, double v, double w, double *ux,
+                   double *uy);
+
+/* Action noise of robot i at step t_global: one uniform draw per coordinate
+ * in [-action_noise, action_noise). */
+void orc_action_noise(const orc_params *p, uint64_t env_id, int64_t t_global, int32_t i,
+                      double *nx, double *ny);
+
+/* Nominal single-integrator command of every robot (before the magnitude
+ * pre-clip): the controller's command plus the action noise. actions may be
+ * NULL (drawn from the stream); the used actions go to actions_used (may be
+ * NULL). */
+void orc_nominal_command(const orc_params *p, int32_t n, uint64_t env_id, int64_t t_global,
+                         const double *x, const double *y, const double *th, const double *gx,
+                         const double *gy, const uint8_t *actions, uint8_t *actions_used,
+                         double *unx, double *uny);
 
 /* Single-integrator command at the projection point -> unicycle (v, w), then
  * optional wheel saturation. */
