@@ -50,7 +50,7 @@ typedef enum {
 } rs_status;
 
 enum { RS_F32 = 0, RS_F64 = 1 };
-enum { RS_CTRL_DISCRETE = 0, RS_CTRL_GOTO = 1 };
+enum { RS_CTRL_DISCRETE = 0, RS_CTRL_GOTO = 1, RS_CTRL_WAYPOINT = 2 };
 enum { RS_MAX_ROBOTS = 16 };
 
 /* Simulation constants (host struct, copied at each call). Units: m, s, rad.
@@ -59,7 +59,8 @@ enum { RS_MAX_ROBOTS = 16 };
  * 0.17, wall gain factor 0.4, |u_k| <= 0.2 and |u_nom| <= 0.2, discrete move
  * speed 0.2, go-to-goal gain 1, wheel radius 0.016 and axle 0.105 (wheel
  * speed limit v_max / R), goal radius 0.05, 500-step episodes, reset lattice
- * 1e-4 m inside a 0.2 m margin with 0.3 m separation. */
+ * 1e-4 m inside a 0.2 m margin with 0.3 m separation; waypoints 0.2 ahead,
+ * position controller gains k_v 0.8 and k_w pi/2; no action noise. */
 typedef struct {
   double x_min, x_max, y_min, y_max;
   double dt;
@@ -77,10 +78,14 @@ typedef struct {
   double min_sep;
   double grid;
   int32_t max_steps;   /* <= 0 disables the time limit */
-  int32_t controller;  /* RS_CTRL_DISCRETE or RS_CTRL_GOTO */
+  int32_t controller;  /* RS_CTRL_DISCRETE, RS_CTRL_GOTO or RS_CTRL_WAYPOINT */
   int32_t dtype;       /* RS_F32 or RS_F64 */
   int32_t qp_max_iters; /* cap on active-set iterations per env; 0 = 8N+32 */
   uint64_t seed;       /* key of the counter-based stream */
+  double waypoint_step; /* RS_CTRL_WAYPOINT: waypoint distance of a move action */
+  double pos_gain;     /* RS_CTRL_WAYPOINT: k_v (linear speed per metre to go) */
+  double ang_gain;     /* RS_CTRL_WAYPOINT: k_w (turn rate at a 90-degree bearing) */
+  double action_noise; /* sigma of the uniform action noise; 0 disables it */
 } rs_params;
 
 /* Environment batch: device structure-of-arrays views, caller-owned. */
@@ -107,6 +112,9 @@ typedef struct rs_ctx rs_ctx;
 typedef struct rs_plan rs_plan;
 
 void rs_params_default(rs_params *p);
+/* Validates p as every call does (host only, no device work): RS_OK or
+ * RS_ERR_INVALID_ARG with the reason in rs_last_error(). */
+rs_status rs_params_check(const rs_params *p);
 const char *rs_status_string(rs_status s);
 /* Message of the last failed call on this host thread ("" if none). */
 const char *rs_last_error(void);
@@ -140,7 +148,17 @@ rs_status env_reset(rs_ctx *ctx, const rs_params *p, const rs_batch *b, const ui
  *     p_i = (x_i + l cos th_i, y_i + l sin th_i): discrete move
  *     action_speed * {0, +x, -x, +y, -y}[a_i] (actions NULL: a_i =
  *     floor(5 r / 2^32), r = word i&3 of block (env_id, t_global, i>>2, 0)),
- *     or kp (g_i - p_i) for RS_CTRL_GOTO; magnitude clipped to v_max;
+ *     or kp (g_i - p_i) for RS_CTRL_GOTO, or for RS_CTRL_WAYPOINT (waypoint
+ *     actions followed by a unicycle position controller: Sec. 6.1 and the
+ *     scenario appendix) the waypoint w_i = (x_i, y_i) + waypoint_step *
+ *     {0, +x, -x, +y, -y}[a_i] steered to by v = k_v rho cos(alpha),
+ *     w = k_w sin(alpha) (rho = |w_i - (x_i, y_i)|, alpha = bearing of w_i
+ *     from the heading; v = w = 0 at the waypoint), taken to the projection
+ *     point as (v cos th - l w sin th, v sin th + l w cos th); then, when
+ *     action_noise = sigma > 0 (action-noise domain randomisation, Sec. 7),
+ *     plus sigma (2 u - 1) per coordinate with u the 24-bit uniforms of
+ *     words 0 (x) and 1 (y) of block (env_id, t_global, 6<<24 | i, 0);
+ *     magnitude clipped to v_max;
  *  2. barrier certificate: u = argmin |u - u_nom|^2 subject to, for i<j,
  *     -2 D.u_i + 2 D.u_j <= gamma (|D|^2 - r_s^2)^3 with D = p_i - p_j, and
  *     per coordinate lo <= u <= hi where hi_x = min(v_max, c_b gamma
@@ -177,8 +195,9 @@ rs_status barrier_certificate(rs_ctx *ctx, const rs_params *p, int32_t num_envs,
 
 /* ---------------------------------------------------------------------------
  * rollout -- `horizon` fused policy steps in one persistent launch (FP32 state,
- * RS_CTRL_DISCRETE). For t = 0..H-1: obs_t of the current state; logits =
- * MLP(bf16(obs_t)) with bf16 weights and activations and FP32 accumulation;
+ * RS_CTRL_DISCRETE or RS_CTRL_WAYPOINT, action noise as set). For t = 0..H-1:
+ * obs_t of the current state; logits = MLP(bf16(obs_t)) with bf16 weights
+ * and activations and FP32 accumulation;
  * a_t drawn by inverse CDF of softmax(logits) with the 24-bit uniform of word
  * i&3 of block (env_id, t_global0 + t, 1<<24 | i>>2, 0); then env_step with a_t
  * (stream time t_global0 + t). Outputs: obs [H][E*N][2N+4] float (may be NULL),
@@ -237,7 +256,8 @@ rs_status env_reset_mixed(rs_ctx *ctx, const rs_params *p, const rs_plan *plan,
 
 /* ---------------------------------------------------------------------------
  * env_run -- `steps` consecutive env_step calls with drawn actions for a mixed
- * batch in ONE persistent launch (FP32). Env e runs
+ * batch in ONE persistent launch (FP32; RS_CTRL_DISCRETE or RS_CTRL_WAYPOINT,
+ * action noise as set). Env e runs
  * steps_per_env ? min(steps, steps_per_env[e]) : steps steps, with stream time
  * t_start[e] + k (t_start NULL: t_global0 + k) at its k-th step. Outputs (each
  * may be NULL): reward_out/done_out [steps][E] (rows past an env's own count

@@ -7,6 +7,11 @@
   uneven_8192      8192 envs, N in {2,4,6,8,12} (0.1/0.3/0.3/0.2/0.1), 1000
                    steps: one persistent env_run launch (default and autotuned
                    schedule) vs per-size env_step launches (5 per step)
+  rollout_waypoint_noise
+                   the fused 16384 x 8 x 128 policy rollout with waypoint
+                   actions (unicycle position controller) and action noise,
+                   beside the same rollout with discrete moves and no noise
+                   (kernel ms per launch from HIP events, robot-steps/s)
   serving          Poisson rollout requests (64-4096 envs log-uniform, N in
                    3..16, horizon 50-500): continuous batching vs plain
                    per-request per-step launches; p50/p99 latency + robot-steps/s
@@ -271,15 +276,65 @@ def serving(R, ctx, seed=0, count=600, skip=60, budget=16 << 30, tick=32, rate=N
             "plain_robot_steps_per_s": work_p / wall_p}
 
 
-def run_all(path, seed=0, which=("single_env_f64", "uniform_4096x4", "uneven_8192", "serving")):
+def rollout_waypoint_noise(R, ctx, seed=0, launches=10, E=16384, n=8, H=128, sigma=0.05):
+    import torch
+
+    from paper_2505_06771_amd import synth
+
+    D = 2 * n + 4
+    w = synth.policy_weights(seed, D)
+    bf = lambda a: torch.from_numpy(a).to(torch.bfloat16).cuda().contiguous()
+    fl = lambda a: torch.from_numpy(a).float().cuda().contiguous()
+    pol = R.Policy(bf(w["w1"]), fl(w["b1"]), bf(w["w2"]), fl(w["b2"]), bf(w["w3"]), fl(w["b3"]))
+    obs = torch.empty(H * E * n * D, device="cuda")
+    act = torch.empty(H * E * n, dtype=torch.uint8, device="cuda")
+    rew = torch.empty(H * E, device="cuda")
+    done = torch.empty(H * E, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    # HBM bytes per launch: obs + action per robot-step, reward + done per
+    # env-step, state in and out once, weights once
+    algo = (H * (E * n * (4 * D + 1) + E * 5) + 2 * (E * n * 20 + E * 8)
+            + 2 * (D * 64 + 64 * 64 + 64 * 5) + 4 * (64 + 64 + 5))
+    res = {"config": "rollout_waypoint_noise", "envs": E, "robots": n, "horizon": H,
+           "launches": launches, "action_noise": sigma}
+    for name, kw in (("discrete", {}),
+                     ("waypoint_noise", {"controller": R.RS_CTRL_WAYPOINT, "action_noise": sigma})):
+        p = R.params(seed=seed, **kw)
+        b = R.Batch.empty(E, n)
+        R.env_reset(ctx, p, b)
+        for k in range(2):
+            R.rollout(ctx, p, b, pol, H, k * H, obs, act, rew, done, stream=stream)
+        _sync()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(launches)]
+        for k in range(launches):
+            ev[k][0].record(stream)
+            R.rollout(ctx, p, b, pol, H, (2 + k) * H, obs, act, rew, done, stream=stream)
+            ev[k][1].record(stream)
+        _sync()
+        ms = sorted(a.elapsed_time(z) for a, z in ev)
+        med = ms[len(ms) // 2]
+        res[f"kernel_ms_median_{name}"] = med
+        res[f"robot_steps_per_s_{name}"] = E * n * H / (med * 1e-3)
+        res[f"hbm_frac_{name}"] = algo / (med * 1e-3) / 8e12
+    res["algorithmic_bytes_per_launch"] = algo
+    return res
+
+
+def run_all(path, seed=0, which=("single_env_f64", "uniform_4096x4", "uneven_8192",
+                                 "rollout_waypoint_noise", "serving")):
     import os
+
+    import torch
 
     from paper_2505_06771_amd import robostep as R
 
+    torch.cuda.init()  # torch first: its tensors and the library share the device
     ctx = R.Context(0)
     os.makedirs(os.path.dirname(path), exist_ok=True)
     fns = {"single_env_f64": single_env_f64, "uniform_4096x4": uniform_4096x4,
-           "uneven_8192": uneven_8192, "serving": serving}
+           "uneven_8192": uneven_8192, "rollout_waypoint_noise": rollout_waypoint_noise,
+           "serving": serving}
     with open(path, "w") as f:
         for name in which:
             _log(f"[suite] {name} ...")
@@ -298,4 +353,5 @@ if __name__ == "__main__":
     ap.add_argument("--only", nargs="*")
     a = ap.parse_args()
     run_all(a.out, which=tuple(a.only) if a.only else
-            ("single_env_f64", "uniform_4096x4", "uneven_8192", "serving"))
+            ("single_env_f64", "uniform_4096x4", "uneven_8192", "rollout_waypoint_noise",
+             "serving"))

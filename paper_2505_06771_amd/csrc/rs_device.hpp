@@ -47,7 +47,7 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
   return c;
 }
 
-enum : uint32_t { kAction = 0, kPolicy = 1, kPose = 2, kGoal = 3, kHeading = 4 };
+enum : uint32_t { kAction = 0, kPolicy = 1, kPose = 2, kGoal = 3, kHeading = 4, kNoise = 6 };
 
 __device__ __forceinline__ uint4 stream_block(uint32_t k0, uint32_t k1, uint32_t w0, uint32_t w1,
                                               uint32_t purpose, uint32_t index, uint32_t w3) {
@@ -58,8 +58,11 @@ __device__ __forceinline__ uint32_t word(uint4 v, int k) {
   return k == 0 ? v.x : (k == 1 ? v.y : (k == 2 ? v.z : v.w));
 }
 
-// 24-bit uniform in [0, 1): exact in FP32.
+// 24-bit uniform in [0, 1): exact in FP32 (and in FP64).
 __device__ __forceinline__ float unit24(uint32_t r) { return (float)(r >> 8) * 5.9604644775390625e-8f; }
+template <typename T> __device__ __forceinline__ T unit24_t(uint32_t r) {
+  return (T)(r >> 8) * T(5.9604644775390625e-8);
+}
 
 // ---- lane-group primitives (groups are aligned blocks of G lanes) ----------
 template <int G, typename T> __device__ __forceinline__ T group_sum(T v) {
@@ -191,6 +194,8 @@ template <int B, int E, typename F> __device__ __forceinline__ void static_for(F
 template <typename T> struct SimConst {
   T xwl, xwh, ywl, ywh;  // walls pulled in by r_s/2: x_min + r_s/2, x_max - r_s/2, ...
   T dt, l, inv_l, gamma, rs2, kb, vmax, vmax4, aspeed, kp;
+  T wstep, kv, kw;  // waypoint distance and position-controller gains
+  T noise;          // action-noise amplitude (0: off)
   T R, halfL, wheel_lim;  // R <= 0: no saturation; halfL = L/2
   T inv_R, R_over_L;  // 1/R and R/L
   T goal_r;

@@ -82,6 +82,11 @@ namespace rs {
 
 rs_status check_params(const rs_params *p);
 
+// Controllers whose nominal command comes from a per-robot action.
+inline bool action_driven(int controller) {
+  return controller == RS_CTRL_DISCRETE || controller == RS_CTRL_WAYPOINT;
+}
+
 template <typename T> SimConst<T> make_const(const rs_params &p) {
   SimConst<T> C;
   C.xwl = (T)(p.x_min + 0.5 * p.safety_radius);
@@ -98,6 +103,10 @@ template <typename T> SimConst<T> make_const(const rs_params &p) {
   C.vmax4 = (T)(4.0 * p.v_max);
   C.aspeed = (T)p.action_speed;
   C.kp = (T)p.kp;
+  C.wstep = (T)p.waypoint_step;
+  C.kv = (T)p.pos_gain;
+  C.kw = (T)p.ang_gain;
+  C.noise = (T)p.action_noise;
   const bool sat = p.wheel_radius > 0.0 && p.base_length > 0.0;
   C.R = sat ? (T)p.wheel_radius : T(0);
   C.halfL = sat ? (T)(0.5 * p.base_length) : T(0);

@@ -35,8 +35,14 @@ rs_status check_params(const rs_params *p) {
   RS_CHECK_ARG(p->barrier_gain > 0 && p->safety_radius > 0, "barrier gain, safety radius must be > 0");
   RS_CHECK_ARG(p->grid > 0, "grid must be > 0");
   RS_CHECK_ARG(p->dtype == RS_F32 || p->dtype == RS_F64, "dtype must be RS_F32 or RS_F64");
-  RS_CHECK_ARG(p->controller == RS_CTRL_DISCRETE || p->controller == RS_CTRL_GOTO,
+  RS_CHECK_ARG(p->controller == RS_CTRL_DISCRETE || p->controller == RS_CTRL_GOTO ||
+                   p->controller == RS_CTRL_WAYPOINT,
                "unknown controller %d", p->controller);
+  RS_CHECK_ARG(p->waypoint_step >= 0 && p->pos_gain >= 0 && p->ang_gain >= 0,
+               "waypoint step and controller gains must be >= 0");
+  RS_CHECK_ARG(p->controller != RS_CTRL_WAYPOINT || p->waypoint_step > 0,
+               "the waypoint controller needs waypoint_step > 0");
+  RS_CHECK_ARG(p->action_noise >= 0 && p->action_noise <= 1e3, "action_noise must be in [0, 1e3]");
   RS_CHECK_ARG(p->qp_max_iters >= 0, "qp_max_iters must be >= 0");
   const double xlo = std::llround((p->x_min + p->reset_margin) / p->grid);
   const double xhi = std::llround((p->x_max - p->reset_margin) / p->grid);
@@ -84,13 +90,13 @@ __global__ __launch_bounds__(kBlock) void k_env_step(StepArgs<T> A) {
   const uint32_t env_id = A.env_base + (uint32_t)e;
   const ConstRef<T> K = kernarg_const<T>(offsetof(StepArgs<T>, C));
   int action = 0;
-  if (A.C.controller == 0)
+  if (A.C.controller != RS_CTRL_GOTO)
     action = A.actions ? (int)A.actions[r]
                        : drawn_action(K.get()->key0, K.get()->key1, env_id, A.t_global, i);
   T s, c;
   sincos_t(th, &s, &c);
   StepOut<T> out = env_step_group<T, G>(K, A.C.qp_cap, &qs[threadIdx.x / G], lane, i, N, on,
-                                        env_id, action, x, y, th, c, s, gx, gy, step, episode,
+                                        env_id, (uint32_t)A.t_global, action, x, y, th, c, s, gx, gy, step, episode,
                                         A.maxviol != nullptr);
   if (on) {
     A.x[r] = x; A.y[r] = y; A.th[r] = th; A.gx[r] = gx; A.gy[r] = gy;
@@ -331,6 +337,15 @@ void rs_params_default(rs_params *p) {
   p->dtype = RS_F32;
   p->qp_max_iters = 0;
   p->seed = 0;
+  p->waypoint_step = 0.2;
+  p->pos_gain = 0.8;
+  p->ang_gain = 1.5707963267948966;
+  p->action_noise = 0.0;
+}
+
+rs_status rs_params_check(const rs_params *p) {
+  clear_error();
+  return check_params(p);
 }
 
 const char *rs_status_string(rs_status s) {
@@ -386,7 +401,6 @@ rs_status env_step(rs_ctx *ctx, const rs_params *p, const rs_batch *b, const uin
   if (s != RS_OK) return s;
   s = check_batch(b, p->dtype, true);
   if (s != RS_OK) return s;
-  RS_CHECK_ARG(p->controller == RS_CTRL_GOTO || true, "");
   hipStream_t st = (hipStream_t)stream;
   if (p->dtype == RS_F64)
     return do_env_step<double>(p, b, actions, t_global, obs, reward, done, max_violation,

@@ -61,7 +61,7 @@ __device__ void run_tile(const RunArgs &A, char *wave_lds, int lane, int first, 
     const auto *P = K.get();
     const int action = drawn_action(P->key0, P->key1, env_id, (uint32_t)(tb + k), i);
     const StepOut<float> so = env_step_group<float, G>(K, qp_cap, sh, lane, i, N, on, env_id,
-                                                       action, x, y, th, c, s, gx, gy, step,
+                                                       (uint32_t)(tb + k), action, x, y, th, c, s, gx, gy, step,
                                                        episode, false);
     rsum += so.reward;
     if (i == 0) {
@@ -187,7 +187,7 @@ static rs_status check_mixed(const rs_ctx *ctx, const rs_params *p, const rs_pla
   rs_status s = check_params(p);
   if (s != RS_OK) return s;
   RS_CHECK_ARG(p->dtype == RS_F32, "mixed batches run in FP32");
-  RS_CHECK_ARG(p->controller == RS_CTRL_DISCRETE, "env_run drives the discrete controller");
+  RS_CHECK_ARG(action_driven(p->controller), "env_run draws actions: discrete or waypoint controller");
   RS_CHECK_ARG(b->num_envs == plan->num_envs, "batch has %d envs, plan %d", b->num_envs,
                plan->num_envs);
   RS_CHECK_ARG(b->x && b->y && b->theta && b->goal_x && b->goal_y && b->step && b->episode,
@@ -349,8 +349,8 @@ rs_status rs_autotune(rs_ctx *ctx, const rs_params *p, const int32_t *robots, in
   RS_CHECK_ARG(envs >= 1 && steps >= 1 && tol > 0, "envs, steps, tol must be > 0");
   rs_status s = check_params(p);
   if (s != RS_OK) return s;
-  RS_CHECK_ARG(p->dtype == RS_F32 && p->controller == RS_CTRL_DISCRETE,
-               "autotune runs the FP32 discrete-controller path");
+  RS_CHECK_ARG(p->dtype == RS_F32 && action_driven(p->controller),
+               "autotune runs the FP32 path of an action-driven controller");
   for (int32_t k = 0; k < count; ++k)
     RS_CHECK_ARG(robots[k] >= 2 && robots[k] <= RS_MAX_ROBOTS, "robots[%d] = %d outside 2..16",
                  k, robots[k]);

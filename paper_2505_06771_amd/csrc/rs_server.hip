@@ -306,8 +306,8 @@ rs_status rs_server_create(rs_ctx *ctx, const rs_params *p, int64_t hbm_budget_b
   RS_CHECK_ARG(ctx != nullptr && out != nullptr, "ctx/out is NULL");
   rs_status st = check_params(p);
   if (st != RS_OK) return st;
-  RS_CHECK_ARG(p->dtype == RS_F32 && p->controller == RS_CTRL_DISCRETE,
-               "the server runs the FP32 discrete-controller path");
+  RS_CHECK_ARG(p->dtype == RS_F32 && action_driven(p->controller),
+               "the server runs the FP32 path of an action-driven controller");
   RS_CHECK_ARG(hbm_budget_bytes >= 4096, "budget too small");
   RS_CHECK_ARG(tick_steps >= 1, "tick_steps must be >= 1");
   *out = nullptr;

@@ -181,14 +181,15 @@ template <typename T> struct StepOut {
 
 // One env step for the group (all lanes call together). State (x, y, th,
 // gx, gy, c = cos th, s = sin th) is updated in place; `action` is the lane's
-// discrete action (ignored for the go-to-goal controller). `step`/`episode`
-// are group-uniform and updated. Observation of the post-step state is left
-// to the caller (c, s are refreshed).
+// action (ignored by the go-to-goal controller); `t` is the stream time of
+// the step (keys the action noise). `step`/`episode` are group-uniform and
+// updated. Observation of the post-step state is left to the caller (c, s
+// are refreshed).
 template <typename T, int G>
 __device__ StepOut<T> env_step_group(ConstRef<T> K, int qp_cap, QPScratch<T, G> *sh, int lane,
-                                     int i, int N, bool on, uint32_t env_id, int action, T &x, T &y,
-                                     T &th, T &c, T &s, T &gx, T &gy, int &step, int &episode,
-                                     bool want_viol) {
+                                     int i, int N, bool on, uint32_t env_id, uint32_t t, int action,
+                                     T &x, T &y, T &th, T &c, T &s, T &gx, T &gy, int &step,
+                                     int &episode, bool want_viol) {
   StepOut<T> out;
   // Constants are read from the kernel arguments phase by phase (see
   // ConstRef), so that they do not hold scalar registers across the step.
@@ -202,10 +203,30 @@ __device__ StepOut<T> env_step_group(ConstRef<T> K, int qp_cap, QPScratch<T, G> 
   } else {
     int ddx, ddy;
     move_dir(action, ddx, ddy);
-    unx = C.aspeed * T(ddx);
-    uny = C.aspeed * T(ddy);
+    if (C.controller == 2) {
+      // Waypoint wstep ahead of the centre along the move (Sec. 6.1, waypoint
+      // actions), steered to by the unicycle position controller
+      // v = kv rho cos(alpha), w = kw sin(alpha). The waypoint lies on a unit
+      // axis d, so rho cos(alpha) = wstep d.(c, s) and sin(alpha) =
+      // (c, s) x d; the stay action (d = 0) gives v = w = 0. The unicycle
+      // command moves the projection point at v (c, s) + l w (-s, c).
+      const T v = C.kv * C.wstep * (c * T(ddx) + s * T(ddy));
+      const T w = C.kw * (c * T(ddy) - s * T(ddx));
+      unx = v * c - C.l * w * s;
+      uny = v * s + C.l * w * c;
+    } else {
+      unx = C.aspeed * T(ddx);
+      uny = C.aspeed * T(ddy);
+    }
   }
-  preclip(C, unx, uny);
+  if (C.noise > T(0)) {
+    // action noise (Sec. 7, domain randomisation): uniform in [-sigma, sigma)
+    // per coordinate, words 0 and 1 of block (env_id, t, kNoise, i)
+    const uint4 o = stream_block(C.key0, C.key1, env_id, t, kNoise, (uint32_t)i, 0u);
+    unx += C.noise * (T(2) * unit24_t<T>(o.x) - T(1));
+    uny += C.noise * (T(2) * unit24_t<T>(o.y) - T(1));
+  }
+  preclip(*K.get(), unx, uny);
   T lox, hix, loy, hiy;
   wall_bounds(*K.get(), px, py, lox, hix, loy, hiy);
   T ux, uy;

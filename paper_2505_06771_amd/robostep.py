@@ -16,7 +16,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "librobostep.so")
 
 RS_F32, RS_F64 = 0, 1
-RS_CTRL_DISCRETE, RS_CTRL_GOTO = 0, 1
+RS_CTRL_DISCRETE, RS_CTRL_GOTO, RS_CTRL_WAYPOINT = 0, 1, 2
 STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "out of memory",
           4: "device error", 5: "over budget", 6: "not found"}
 
@@ -41,6 +41,8 @@ class RsParams(ctypes.Structure):
         ("max_steps", ctypes.c_int32), ("controller", ctypes.c_int32),
         ("dtype", ctypes.c_int32), ("qp_max_iters", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
+        ("waypoint_step", ctypes.c_double), ("pos_gain", ctypes.c_double),
+        ("ang_gain", ctypes.c_double), ("action_noise", ctypes.c_double),
     ]
 
 
@@ -97,6 +99,7 @@ def lib():
     P = ctypes.POINTER
     sig = {
         "rs_params_default": (None, [P(RsParams)]),
+        "rs_params_check": (i32, [P(RsParams)]),
         "rs_status_string": (ctypes.c_char_p, [i32]),
         "rs_last_error": (ctypes.c_char_p, []),
         "rs_create": (i32, [ctypes.c_int, P(_VP)]),

@@ -60,7 +60,8 @@ def test_params_struct_matches_oracle_constants(R):
     p = R.params()
     for f in ("x_min", "x_max", "dt", "proj_dist", "barrier_gain", "safety_radius",
               "boundary_gain_factor", "v_max", "action_speed", "kp", "wheel_radius",
-              "base_length", "goal_radius", "reset_margin", "min_sep", "grid", "max_steps"):
+              "base_length", "goal_radius", "reset_margin", "min_sep", "grid", "max_steps",
+              "waypoint_step", "pos_gain", "ang_gain", "action_noise"):
         assert getattr(o, f) == getattr(p, f), f
 
 
@@ -69,7 +70,8 @@ def test_struct_layouts_match_the_header(R, tmp_path):
     import subprocess
 
     src = tmp_path / "sizes.c"
-    fields = {"rs_params": ["seed", "qp_max_iters", "grid"], "rs_batch": ["env_id_base", "episode"],
+    fields = {"rs_params": ["seed", "qp_max_iters", "grid", "waypoint_step", "action_noise"],
+              "rs_batch": ["env_id_base", "episode"],
               "rs_policy": ["in_dim", "b3"], "rs_schedule": ["qp_iters", "lanes_per_env"],
               "rs_request_info": ["finish_time", "horizon"],
               "rs_server_stats": ["running", "peak_bytes"]}
@@ -154,3 +156,19 @@ def test_snapshot_size_and_argument_checks(R):
     # buffer too small
     assert L.rs_snapshot(fake, R.RS_F32, ctypes.byref(b), 40, buf.ctypes.data, n - 1, None) == 1
     assert L.rs_snapshot(None, R.RS_F32, ctypes.byref(b), 40, buf.ctypes.data, n, None) == 1
+
+
+def test_params_check_covers_controllers_and_noise(R):
+    """Parameter validation runs on the host, before any device work."""
+    L = R.lib()
+    ok = lambda **kw: L.rs_params_check(ctypes.byref(R.params(**kw)))
+    assert ok() == 0
+    assert ok(controller=R.RS_CTRL_WAYPOINT, action_noise=0.05) == 0
+    assert ok(controller=R.RS_CTRL_GOTO) == 0
+    assert ok(controller=3) == 1 and b"controller" in L.rs_last_error()
+    assert ok(controller=R.RS_CTRL_WAYPOINT, waypoint_step=0.0) == 1
+    assert b"waypoint_step" in L.rs_last_error()
+    assert ok(action_noise=-0.1) == 1 and b"action_noise" in L.rs_last_error()
+    assert ok(pos_gain=-1.0) == 1
+    assert ok(dt=0.0) == 1
+    assert ok() == 0 and L.rs_last_error() == b""

@@ -47,7 +47,9 @@ def test_reset_mixed_matches_oracle(orc):
         assert angle_diff(th[off[e]:off[e + 1]], oth).max() <= 1e-6
 
 
-def test_env_run_one_step_teacher_forced(orc):
+@pytest.mark.parametrize("extra", [{}, {"controller": 2, "action_noise": 0.05}],
+                         ids=["discrete", "waypoint_noise"])
+def test_env_run_one_step_teacher_forced(orc, extra):
     import torch
 
     R, ctx = ctx_and_lib()
@@ -57,8 +59,8 @@ def test_env_run_one_step_teacher_forced(orc):
     # push the step counters near the time limit so resets happen
     b.step.copy_(torch.from_numpy(np.random.default_rng(0).integers(490, 500, E).astype(np.int32)).cuda())
     off = _offsets(counts)
-    po = orc.Params(seed=6)
-    p = R.params(seed=6)
+    po = orc.Params(seed=6, **extra)
+    p = R.params(seed=6, **extra)
     rew = torch.zeros(E, device="cuda")
     done = torch.zeros(E, dtype=torch.uint8, device="cuda")
     total_obs = sum(int(n) * (2 * int(n) + 4) for n in counts)

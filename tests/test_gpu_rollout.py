@@ -44,7 +44,8 @@ def _cdf_margin(logits, u):
     return np.abs(np.cumsum(pr)[:4] - u).min()
 
 
-def run_and_check(orc, n, E, H, seed, sample_envs=None, sample_steps=None, step0=None):
+def run_and_check(orc, n, E, H, seed, sample_envs=None, sample_steps=None, step0=None,
+                  extra=None):
     import torch
 
     R, ctx = ctx_and_lib()
@@ -64,8 +65,9 @@ def run_and_check(orc, n, E, H, seed, sample_envs=None, sample_steps=None, step0
     done = torch.zeros(H * E, dtype=torch.uint8, device="cuda")
     step_init = host(b.step).astype(np.int32).copy()
     ep_init = host(b.episode).astype(np.int32).copy()
-    p = R.params(seed=seed)
-    po = orc.Params(seed=seed)
+    extra = extra or {}
+    p = R.params(seed=seed, **extra)
+    po = orc.Params(seed=seed, **extra)
     t0 = 1000
     banner(f"rollout n={n} E={E} H={H}")
     R.rollout(ctx, p, b, pol, H, t0, obs, act, rew, done)
@@ -128,6 +130,17 @@ def run_and_check(orc, n, E, H, seed, sample_envs=None, sample_steps=None, step0
     print(f"rollout n={n}: actions {nact}, band mismatches {nband}, worst pose gap {worst:.3g}")
     assert nband <= max(2, 0.005 * nact)
     return b, ob, ac, rw, dn
+
+
+@pytest.mark.parametrize("n", [4, 8])
+def test_rollout_waypoint_and_action_noise(orc, n):
+    """Policy actions as waypoints for the unicycle position controller, with
+    uniform action noise (sigma 0.05 m/s)."""
+    E = {4: 67, 8: 131}[n]
+    rng = np.random.default_rng(50 + n)
+    step0 = rng.integers(470, 500, E).astype(np.int32)
+    run_and_check(orc, n, E, H=40, seed=60 + n, step0=step0,
+                  extra=dict(controller=2, action_noise=0.05))
 
 
 @pytest.mark.parametrize("n", [2, 3, 4, 6, 8, 14])

@@ -197,6 +197,33 @@ def test_env_step_teacher_forced_f32(orc, n):
     assert s["resets"] >= E // 2
 
 
+@pytest.mark.parametrize("kind,n,controller", [("f32", 3, 2), ("f32", 8, 2), ("f32", 6, 0),
+                                               ("f64", 5, 2)])
+def test_env_step_waypoint_and_action_noise(orc, kind, n, controller):
+    """Waypoint actions through the unicycle position controller and uniform
+    action noise (sigma 0.05 m/s), teacher-forced against the oracle."""
+    import torch
+
+    R, ctx = ctx_and_lib()
+    tdt, _ = _dtypes(torch, kind)
+    E = 97
+    st = _mixed_states(300 + n, E, n)
+    rng = np.random.default_rng(40 + n)
+    step0 = rng.integers(480, 500, E).astype(np.int32)
+    b = batch_from_states(R, st, n, tdt, env_id_base=900, step=step0,
+                          episode=rng.integers(0, 3, E).astype(np.int32))
+    kw = dict(controller=controller, action_noise=0.05, seed=13)
+    p = R.params(dtype=R.RS_F64 if kind == "f64" else R.RS_F32, **kw)
+    po = orc.Params(**kw)
+    tol = ({"xy": 1e-5, "th": 6.6e-5, "obs": 1e-5} if kind == "f32"
+           else {"xy": 1e-9, "th": 1e-9, "obs": 1e-9})
+    banner(f"env_step controller {controller} + noise {kind} n={n}")
+    s = _step_compare(orc, po, R, ctx, p, b, n, steps=30, t0=50, tol=tol,
+                      explicit_actions=(n == 3))
+    print(s)
+    assert s["resets"] >= E // 2
+
+
 def test_env_step_explicit_actions_match_drawn(orc):
     import torch
 
@@ -297,3 +324,7 @@ def test_invalid_arguments_are_rejected():
     b = R.Batch.empty(4, 4)
     with pytest.raises(R.RobostepError):
         R.env_step(ctx, R.params(dt=-1.0), b)
+    with pytest.raises(R.RobostepError):
+        R.env_step(ctx, R.params(controller=R.RS_CTRL_WAYPOINT, waypoint_step=0.0), b)
+    with pytest.raises(R.RobostepError):
+        R.env_step(ctx, R.params(action_noise=-1.0), b)
