@@ -48,6 +48,8 @@ class OrcParams(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("waypoint_step", ctypes.c_double), ("pos_gain", ctypes.c_double),
         ("ang_gain", ctypes.c_double), ("action_noise", ctypes.c_double),
+        ("prey_speed", ctypes.c_double), ("tag_radius", ctypes.c_double),
+        ("tag_reward", ctypes.c_double), ("scenario", ctypes.c_int32),
     ]
 
 
@@ -80,6 +82,10 @@ class Params:
     pos_gain: float = 0.8
     ang_gain: float = math.pi / 2
     action_noise: float = 0.0
+    prey_speed: float = 0.3
+    tag_radius: float = 0.25
+    tag_reward: float = 10.0
+    scenario: int = 0
 
     def c(self) -> OrcParams:
         return OrcParams(**{f.name: getattr(self, f.name) for f in fields(self)})
@@ -124,6 +130,11 @@ def lib():
                                        _D]
         L.orc_nominal_command.argtypes = [_P, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64,
                                           _D, _D, _D, _D, _D, _U8, _U8, _D, _D]
+        L.orc_prey_move.argtypes = [_P, ctypes.c_int32, _D, _D, ctypes.c_double,
+                                    ctypes.c_double, _D, _D, _D]
+        L.orc_prey_move.restype = ctypes.c_int32
+        L.orc_tagged.argtypes = [_P, ctypes.c_int32, _D, _D, ctypes.c_double, ctypes.c_double]
+        L.orc_tagged.restype = ctypes.c_int32
         L.orc_observe.argtypes = [ctypes.c_int32, _D, _D, _D, _D, _D, _D]
         L.orc_env_step.argtypes = [_P, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64,
                                    _D, _D, _D, _D, _D, _I32, _I32, _U8, _U8, _D, _D, _U8,
@@ -268,6 +279,23 @@ def nominal_command(p: Params, state: dict, env_id: int, t_global: int, actions=
                               *[_ptr(_f64(state[k]), _D) for k in ("x", "y", "th", "gx", "gy")],
                               _ptr(act, _U8), _ptr(used, _U8), _ptr(unx, _D), _ptr(uny, _D))
     return unx, uny, (used if act is None else act)
+
+
+def prey_move(p: Params, x, y, qx: float, qy: float):
+    """Predator-Prey prey move: returns (new qx, new qy, chosen index, scores[17])."""
+    x, y = _f64(x), _f64(y)
+    nqx, nqy = ctypes.c_double(), ctypes.c_double()
+    scores = np.zeros(17)
+    cp = p.c()
+    k = lib().orc_prey_move(ctypes.byref(cp), x.size, _ptr(x, _D), _ptr(y, _D), qx, qy,
+                            ctypes.byref(nqx), ctypes.byref(nqy), _ptr(scores, _D))
+    return nqx.value, nqy.value, k, scores
+
+
+def tagged(p: Params, x, y, qx: float, qy: float) -> bool:
+    x, y = _f64(x), _f64(y)
+    cp = p.c()
+    return bool(lib().orc_tagged(ctypes.byref(cp), x.size, _ptr(x, _D), _ptr(y, _D), qx, qy))
 
 
 def observe(x, y, th, gx, gy):

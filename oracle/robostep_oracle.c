@@ -7,6 +7,8 @@
  *                          unicycle controllers, barrier-certificate QP.
  *   Appendix, Navigation   observation = own position + vector to goal,
  *                          reward = -1 x distance of robots to their goals.
+ *   Appendix, Predator Prey  taggers, a prey that flees the closest tagger,
+ *                          reward 10 per step with a tag.
  *   Sec. 9 "Limitations"   the simulator's QP solver differs from the testbed's;
  *                          the ground truth here is the exact minimiser.
  * The paper states none of the formulas; the readings used are stated on each
@@ -153,10 +155,13 @@ void orc_reset_env(const orc_params *p, uint64_t env_id, int32_t episode, int32_
   uint32_t hb[ORC_MAX_N];
   orc_reset_lattice(p, env_id, episode, n, X, Y, GX, GY, hb);
   for (int32_t i = 0; i < n; ++i) {
+    /* Predator-Prey: the prey is the goal sampler's first point, shared by
+       every robot's goal slot */
+    int32_t g = p->scenario == 1 ? 0 : i;
     x[i] = (double)X[i] * p->grid;
     y[i] = (double)Y[i] * p->grid;
-    gx[i] = (double)GX[i] * p->grid;
-    gy[i] = (double)GY[i] * p->grid;
+    gx[i] = (double)GX[g] * p->grid;
+    gy[i] = (double)GY[g] * p->grid;
     th[i] = -M_PI + 2.0 * M_PI * unit_uniform(hb[i]);
   }
 }
@@ -584,6 +589,56 @@ void orc_nominal_command(const orc_params *p, int32_t n, uint64_t env_id, int64_
 }
 
 /* ------------------------------------------------------------------------ */
+/* Predator-Prey (Appendix B: N taggers chase a faster prey; the prey takes, */
+/* at every step, the move that keeps it farthest from the closest tagger;   */
+/* a tag is the prey inside some tagger's radius; team reward 10 per tag).   */
+/* Readings: the prey lives in every robot's goal slot (so the observation's */
+/* last pair is the vector to the prey); its candidate moves are staying put */
+/* and a step of prey_speed * dt in each of 16 evenly spaced directions,     */
+/* each clamped to the arena pulled in by r_s/2; it takes the candidate with */
+/* the largest squared distance to the closest robot centre, judged on the   */
+/* centres before the robots move (both move at once), first index on ties. */
+/* A step is tagged when, after both moved, some centre is closer than       */
+/* tag_radius; episodes end on the step limit only.                          */
+/* ------------------------------------------------------------------------ */
+int32_t orc_prey_move(const orc_params *p, int32_t n, const double *x, const double *y, double qx,
+                      double qy, double *nqx, double *nqy, double *scores) {
+  double lox = p->x_min + 0.5 * p->safety_radius, hix = p->x_max - 0.5 * p->safety_radius;
+  double loy = p->y_min + 0.5 * p->safety_radius, hiy = p->y_max - 0.5 * p->safety_radius;
+  double step = p->prey_speed * p->dt;
+  int32_t best = -1;
+  double best_score = -1.0;
+  for (int32_t k = 0; k <= 16; ++k) {
+    double cx = qx, cy = qy;
+    if (k > 0) {
+      double a = 2.0 * M_PI * (double)(k - 1) / 16.0;
+      cx = fmin(fmax(qx + step * cos(a), lox), hix);
+      cy = fmin(fmax(qy + step * sin(a), loy), hiy);
+    }
+    double closest = INFINITY;
+    for (int32_t j = 0; j < n; ++j) {
+      double d2 = (cx - x[j]) * (cx - x[j]) + (cy - y[j]) * (cy - y[j]);
+      if (d2 < closest) closest = d2;
+    }
+    if (scores) scores[k] = closest;
+    if (closest > best_score) {
+      best_score = closest;
+      best = k;
+      *nqx = cx;
+      *nqy = cy;
+    }
+  }
+  return best;
+}
+
+int32_t orc_tagged(const orc_params *p, int32_t n, const double *x, const double *y, double qx,
+                   double qy) {
+  for (int32_t j = 0; j < n; ++j)
+    if (sqrt((x[j] - qx) * (x[j] - qx) + (y[j] - qy) * (y[j] - qy)) < p->tag_radius) return 1;
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* One environment step.                                                     */
 /* ------------------------------------------------------------------------ */
 int32_t orc_env_step(const orc_params *p, int32_t n, uint64_t env_id, int64_t t_global,
@@ -598,6 +653,9 @@ int32_t orc_env_step(const orc_params *p, int32_t n, uint64_t env_id, int64_t t_
     py[i] = y[i] + p->proj_dist * sin(th[i]);
   }
   orc_nominal_command(p, n, env_id, t_global, x, y, th, gx, gy, actions, actions_used, unx, uny);
+  int pp = p->scenario == 1;
+  double nqx = 0.0, nqy = 0.0;
+  if (pp) orc_prey_move(p, n, x, y, gx[0], gy[0], &nqx, &nqy, NULL);
   double mv = 0.0;
   int32_t status = orc_barrier_certificate(p, n, px, py, unx, uny, ux, uy, NULL, NULL, &mv);
   if (infeasible) *infeasible = (uint8_t)(status == 1);
@@ -613,13 +671,23 @@ int32_t orc_env_step(const orc_params *p, int32_t n, uint64_t env_id, int64_t t_
   }
   *step += 1;
   double r = 0.0;
-  int all_near = 1;
-  for (int32_t i = 0; i < n; ++i) {
-    double dist = sqrt((x[i] - gx[i]) * (x[i] - gx[i]) + (y[i] - gy[i]) * (y[i] - gy[i]));
-    r -= dist;
-    if (!(dist < p->goal_radius)) all_near = 0;
+  int finished;
+  if (pp) {
+    for (int32_t i = 0; i < n; ++i) {
+      gx[i] = nqx;
+      gy[i] = nqy;
+    }
+    r = orc_tagged(p, n, x, y, nqx, nqy) ? p->tag_reward : 0.0;
+    finished = p->max_steps > 0 && *step >= p->max_steps;
+  } else {
+    int all_near = 1;
+    for (int32_t i = 0; i < n; ++i) {
+      double dist = sqrt((x[i] - gx[i]) * (x[i] - gx[i]) + (y[i] - gy[i]) * (y[i] - gy[i]));
+      r -= dist;
+      if (!(dist < p->goal_radius)) all_near = 0;
+    }
+    finished = (p->goal_radius > 0.0 && all_near) || (p->max_steps > 0 && *step >= p->max_steps);
   }
-  int finished = (p->goal_radius > 0.0 && all_near) || (p->max_steps > 0 && *step >= p->max_steps);
   if (reward) *reward = r;
   if (done) *done = (uint8_t)finished;
   if (finished) {

@@ -49,6 +49,10 @@ typedef struct {
   double pos_gain;           /* controller 2: k_v, linear speed per metre of distance */
   double ang_gain;           /* controller 2: k_w, turn rate at a 90-degree bearing */
   double action_noise;       /* sigma of the uniform action noise; 0 disables it */
+  double prey_speed;         /* scenario 1: prey speed (m/s) */
+  double tag_radius;         /* scenario 1: a robot centre closer than this tags the prey */
+  double tag_reward;         /* scenario 1: team reward of a step with a tag */
+  int32_t scenario;          /* 0: Navigation, 1: Predator-Prey */
 } orc_params;
 
 /* Philox4x32-10 block cipher (Salmon, Moraes, Dror, Shaw, SC'11). */
@@ -110,6 +114,16 @@ void orc_nominal_command(const orc_params *p, int32_t n, uint64_t env_id, int64_
                          const double *x, const double *y, const double *th, const double *gx,
                          const double *gy, const uint8_t *actions, uint8_t *actions_used,
                          double *unx, double *uny);
+
+/* Predator-Prey: the prey's move from (qx, qy) given the robot centres (x, y):
+ * writes the new position and, if scores is not NULL, the 17 candidate
+ * scores (squared distance of each candidate to the closest robot); returns
+ * the index of the chosen candidate (0 = stay, k = direction 2 pi (k-1)/16). */
+int32_t orc_prey_move(const orc_params *p, int32_t n, const double *x, const double *y, double qx,
+                      double qy, double *nqx, double *nqy, double *scores);
+/* Predator-Prey: 1 when some robot centre is closer than tag_radius to the prey. */
+int32_t orc_tagged(const orc_params *p, int32_t n, const double *x, const double *y, double qx,
+                   double qy);
 
 /* Single-integrator command at the projection point -> unicycle (v, w), then
  * optional wheel saturation. */
