@@ -51,6 +51,7 @@ typedef enum {
 
 enum { RS_F32 = 0, RS_F64 = 1 };
 enum { RS_CTRL_DISCRETE = 0, RS_CTRL_GOTO = 1, RS_CTRL_WAYPOINT = 2 };
+enum { RS_SCN_NAVIGATION = 0, RS_SCN_PREDATOR_PREY = 1 };
 enum { RS_MAX_ROBOTS = 16 };
 
 /* Simulation constants (host struct, copied at each call). Units: m, s, rad.
@@ -60,7 +61,9 @@ enum { RS_MAX_ROBOTS = 16 };
  * speed 0.2, go-to-goal gain 1, wheel radius 0.016 and axle 0.105 (wheel
  * speed limit v_max / R), goal radius 0.05, 500-step episodes, reset lattice
  * 1e-4 m inside a 0.2 m margin with 0.3 m separation; waypoints 0.2 ahead,
- * position controller gains k_v 0.8 and k_w pi/2; no action noise. */
+ * position controller gains k_v 0.8 and k_w pi/2; no action noise;
+ * Navigation scenario (Predator-Prey: prey 0.3 m/s, tag radius 0.25, tag
+ * reward 10). */
 typedef struct {
   double x_min, x_max, y_min, y_max;
   double dt;
@@ -86,6 +89,10 @@ typedef struct {
   double pos_gain;     /* RS_CTRL_WAYPOINT: k_v (linear speed per metre to go) */
   double ang_gain;     /* RS_CTRL_WAYPOINT: k_w (turn rate at a 90-degree bearing) */
   double action_noise; /* sigma of the uniform action noise; 0 disables it */
+  double prey_speed;   /* RS_SCN_PREDATOR_PREY: prey speed */
+  double tag_radius;   /* RS_SCN_PREDATOR_PREY: tag when a centre is closer than this */
+  double tag_reward;   /* RS_SCN_PREDATOR_PREY: team reward of a step with a tag */
+  int32_t scenario;    /* RS_SCN_NAVIGATION or RS_SCN_PREDATOR_PREY */
 } rs_params;
 
 /* Environment batch: device structure-of-arrays views, caller-owned. */
@@ -138,6 +145,8 @@ rs_status rs_destroy(rs_ctx *ctx);
  * the 24-bit uniform of word i&3 of block (env_id, episode, 4<<24 | i>>2, 0).
  * step[e] is set to 0; episode[e] is left as given. obs (may be NULL) gets the
  * observation [E*N][2N+4] of the reset envs (others untouched).
+ * RS_SCN_PREDATOR_PREY: every goal slot of env e gets the prey, the goal
+ * sampler's first point (robot 0's goal).
  * ------------------------------------------------------------------------- */
 rs_status env_reset(rs_ctx *ctx, const rs_params *p, const rs_batch *b, const uint8_t *mask,
                     void *obs, void *stream);
@@ -170,6 +179,15 @@ rs_status env_reset(rs_ctx *ctx, const rs_params *p, const rs_batch *b, const ui
  *     [-pi, pi];
  *  5. step += 1; reward = -sum_i |(x_i, y_i) - g_i|; done = (all distances <
  *     goal_radius) or step >= max_steps; done envs are reset (episode += 1);
+ *     RS_SCN_PREDATOR_PREY (the Predator Prey scenario of the appendix):
+ *     every robot's goal slot holds the env's prey q. Before the robots
+ *     move, the prey takes the candidate, among staying at q and
+ *     clamp(q + prey_speed dt (cos 2 pi k/16, sin 2 pi k/16)) for k = 0..15
+ *     (clamped to the arena pulled in by r_s/2; candidates in that order),
+ *     that maximises the squared distance to the closest robot centre of
+ *     the pre-step state, the first on ties. After both moved, reward =
+ *     tag_reward if some centre is closer than tag_radius to the prey, else
+ *     0; done = step >= max_steps only;
  *  6. obs [E*N][2N+4] of the post-step (post-reset) state, per robot: x, y,
  *     cos th, sin th, (x_j - x_i, y_j - y_i) for j != i ascending, g_i - (x,y).
  * actions: [E*N] uint8 in 0..4 or NULL. reward [E] (float/double), done [E],
@@ -195,7 +213,8 @@ rs_status barrier_certificate(rs_ctx *ctx, const rs_params *p, int32_t num_envs,
 
 /* ---------------------------------------------------------------------------
  * rollout -- `horizon` fused policy steps in one persistent launch (FP32 state,
- * RS_CTRL_DISCRETE or RS_CTRL_WAYPOINT, action noise as set). For t = 0..H-1:
+ * RS_CTRL_DISCRETE or RS_CTRL_WAYPOINT, action noise and scenario as set).
+ * For t = 0..H-1:
  * obs_t of the current state; logits = MLP(bf16(obs_t)) with bf16 weights
  * and activations and FP32 accumulation;
  * a_t drawn by inverse CDF of softmax(logits) with the 24-bit uniform of word
@@ -256,8 +275,8 @@ rs_status env_reset_mixed(rs_ctx *ctx, const rs_params *p, const rs_plan *plan,
 
 /* ---------------------------------------------------------------------------
  * env_run -- `steps` consecutive env_step calls with drawn actions for a mixed
- * batch in ONE persistent launch (FP32; RS_CTRL_DISCRETE or RS_CTRL_WAYPOINT,
- * action noise as set). Env e runs
+ * batch in ONE persistent launch (FP32, Navigation scenario; RS_CTRL_DISCRETE
+ * or RS_CTRL_WAYPOINT, action noise as set). Env e runs
  * steps_per_env ? min(steps, steps_per_env[e]) : steps steps, with stream time
  * t_start[e] + k (t_start NULL: t_global0 + k) at its k-th step. Outputs (each
  * may be NULL): reward_out/done_out [steps][E] (rows past an env's own count

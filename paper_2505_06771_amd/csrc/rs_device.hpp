@@ -181,6 +181,9 @@ template <int G, typename T> __device__ __forceinline__ T gsum(T v) {
 template <int G, typename T> __device__ __forceinline__ T gmax(T v) {
   return gred<G>(v, [](T a, T b) { return a > b ? a : b; });
 }
+template <int G, typename T> __device__ __forceinline__ T gmin(T v) {
+  return gred<G>(v, [](T a, T b) { return a < b ? a : b; });
+}
 
 // Compile-time loop: f(std::integral_constant<int, K>) for K in [B, E).
 template <int B, int E, typename F> __device__ __forceinline__ void static_for(F &&f) {
@@ -196,6 +199,7 @@ template <typename T> struct SimConst {
   T dt, l, inv_l, gamma, rs2, kb, vmax, vmax4, aspeed, kp;
   T wstep, kv, kw;  // waypoint distance and position-controller gains
   T noise;          // action-noise amplitude (0: off)
+  T prey_step, tag_r, tag_reward;  // Predator-Prey: prey move per step, tag radius, reward
   T R, halfL, wheel_lim;  // R <= 0: no saturation; halfL = L/2
   T inv_R, R_over_L;  // 1/R and R/L
   T goal_r;
@@ -204,6 +208,7 @@ template <typename T> struct SimConst {
   T eps_r;            // threshold on the multiplier step direction
   int max_steps;
   int controller;
+  int scenario;       // 0 Navigation, 1 Predator-Prey (kernels are specialised on it)
   int qp_cap;         // 0: 8N + 32
   uint32_t key0, key1;
   // reset lattice (integer units of `grid`)

@@ -107,6 +107,9 @@ template <typename T> SimConst<T> make_const(const rs_params &p) {
   C.kv = (T)p.pos_gain;
   C.kw = (T)p.ang_gain;
   C.noise = (T)p.action_noise;
+  C.prey_step = (T)(p.prey_speed * p.dt);
+  C.tag_r = (T)p.tag_radius;
+  C.tag_reward = (T)p.tag_reward;
   const bool sat = p.wheel_radius > 0.0 && p.base_length > 0.0;
   C.R = sat ? (T)p.wheel_radius : T(0);
   C.halfL = sat ? (T)(0.5 * p.base_length) : T(0);
@@ -120,6 +123,7 @@ template <typename T> SimConst<T> make_const(const rs_params &p) {
   C.eps_r = f32 ? (T)1e-6 : (T)1e-13;
   C.max_steps = p.max_steps;
   C.controller = p.controller;
+  C.scenario = p.scenario;
   C.qp_cap = p.qp_max_iters;
   C.key0 = (uint32_t)p.seed;
   C.key1 = (uint32_t)(p.seed >> 32);

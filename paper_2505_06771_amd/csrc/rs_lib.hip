@@ -43,6 +43,10 @@ rs_status check_params(const rs_params *p) {
   RS_CHECK_ARG(p->controller != RS_CTRL_WAYPOINT || p->waypoint_step > 0,
                "the waypoint controller needs waypoint_step > 0");
   RS_CHECK_ARG(p->action_noise >= 0 && p->action_noise <= 1e3, "action_noise must be in [0, 1e3]");
+  RS_CHECK_ARG(p->scenario == RS_SCN_NAVIGATION || p->scenario == RS_SCN_PREDATOR_PREY,
+               "unknown scenario %d", p->scenario);
+  RS_CHECK_ARG(p->prey_speed >= 0 && p->tag_radius >= 0,
+               "prey_speed and tag_radius must be >= 0");
   RS_CHECK_ARG(p->qp_max_iters >= 0, "qp_max_iters must be >= 0");
   const double xlo = std::llround((p->x_min + p->reset_margin) / p->grid);
   const double xhi = std::llround((p->x_max - p->reset_margin) / p->grid);
@@ -75,7 +79,7 @@ template <typename T> struct StepArgs {
   float *maxviol;
 };
 
-template <typename T, int G>
+template <typename T, int G, bool PP>
 __global__ __launch_bounds__(kBlock) void k_env_step(StepArgs<T> A) {
   __shared__ QPScratch<T, G> qs[kBlock / G];
   const int lane = threadIdx.x & 63;
@@ -95,7 +99,7 @@ __global__ __launch_bounds__(kBlock) void k_env_step(StepArgs<T> A) {
                        : drawn_action(K.get()->key0, K.get()->key1, env_id, A.t_global, i);
   T s, c;
   sincos_t(th, &s, &c);
-  StepOut<T> out = env_step_group<T, G>(K, A.C.qp_cap, &qs[threadIdx.x / G], lane, i, N, on,
+  StepOut<T> out = env_step_group<T, G, PP>(K, A.C.qp_cap, &qs[threadIdx.x / G], lane, i, N, on,
                                         env_id, (uint32_t)A.t_global, action, x, y, th, c, s, gx, gy, step, episode,
                                         A.maxviol != nullptr);
   if (on) {
@@ -125,7 +129,7 @@ template <typename T> struct ResetArgs {
   T *obs;
 };
 
-template <typename T, int G>
+template <typename T, int G, bool PP>
 __global__ __launch_bounds__(kBlock) void k_env_reset(ResetArgs<T> A) {
   const int lane = threadIdx.x & 63;
   const int i = threadIdx.x & (G - 1);
@@ -137,7 +141,7 @@ __global__ __launch_bounds__(kBlock) void k_env_reset(ResetArgs<T> A) {
   const size_t r = (size_t)e * N + (on ? i : 0);
   const int episode = A.episode[e];
   T x, y, th, gx, gy;
-  reset_env<T, G>(kernarg_const<T>(offsetof(ResetArgs<T>, C)), A.env_base + (uint32_t)e,
+  reset_env<T, G, PP>(kernarg_const<T>(offsetof(ResetArgs<T>, C)), A.env_base + (uint32_t)e,
                   (uint32_t)episode, i, N, lane, x, y, th, gx, gy);
   if (on) {
     A.x[r] = x; A.y[r] = y; A.th[r] = th; A.gx[r] = gx; A.gy[r] = gy;
@@ -267,8 +271,13 @@ static rs_status do_env_step(const rs_params *p, const rs_batch *b, const uint8_
   A.obs = (T *)obs; A.reward = (T *)reward; A.done = done; A.infeasible = infeasible;
   A.maxviol = maxviol;
   const int G = pow2_group(A.N);
-  RS_DISPATCH_G(G, hipLaunchKernelGGL((k_env_step<T, GG>), dim3(blocks_for<T>(A.E, GG)),
-                                      dim3(kBlock), 0, st, A));
+  if (p->scenario == RS_SCN_PREDATOR_PREY) {
+    RS_DISPATCH_G(G, hipLaunchKernelGGL((k_env_step<T, GG, true>), dim3(blocks_for<T>(A.E, GG)),
+                                        dim3(kBlock), 0, st, A));
+  } else {
+    RS_DISPATCH_G(G, hipLaunchKernelGGL((k_env_step<T, GG, false>), dim3(blocks_for<T>(A.E, GG)),
+                                        dim3(kBlock), 0, st, A));
+  }
   return launch_status("env_step");
 }
 
@@ -285,8 +294,13 @@ static rs_status do_env_reset(const rs_params *p, const rs_batch *b, const uint8
   A.mask = mask;
   A.obs = (T *)obs;
   const int G = pow2_group(A.N);
-  RS_DISPATCH_G(G, hipLaunchKernelGGL((k_env_reset<T, GG>), dim3(blocks_for<T>(A.E, GG)),
-                                      dim3(kBlock), 0, st, A));
+  if (p->scenario == RS_SCN_PREDATOR_PREY) {
+    RS_DISPATCH_G(G, hipLaunchKernelGGL((k_env_reset<T, GG, true>), dim3(blocks_for<T>(A.E, GG)),
+                                        dim3(kBlock), 0, st, A));
+  } else {
+    RS_DISPATCH_G(G, hipLaunchKernelGGL((k_env_reset<T, GG, false>), dim3(blocks_for<T>(A.E, GG)),
+                                        dim3(kBlock), 0, st, A));
+  }
   return launch_status("env_reset");
 }
 
@@ -341,6 +355,10 @@ void rs_params_default(rs_params *p) {
   p->pos_gain = 0.8;
   p->ang_gain = 1.5707963267948966;
   p->action_noise = 0.0;
+  p->prey_speed = 0.3;
+  p->tag_radius = 0.25;
+  p->tag_reward = 10.0;
+  p->scenario = RS_SCN_NAVIGATION;
 }
 
 rs_status rs_params_check(const rs_params *p) {

@@ -188,6 +188,10 @@ static rs_status check_mixed(const rs_ctx *ctx, const rs_params *p, const rs_pla
   if (s != RS_OK) return s;
   RS_CHECK_ARG(p->dtype == RS_F32, "mixed batches run in FP32");
   RS_CHECK_ARG(action_driven(p->controller), "env_run draws actions: discrete or waypoint controller");
+  if (p->scenario != RS_SCN_NAVIGATION) {
+    set_error("mixed-size batches run the Navigation scenario");
+    return RS_ERR_UNSUPPORTED;
+  }
   RS_CHECK_ARG(b->num_envs == plan->num_envs, "batch has %d envs, plan %d", b->num_envs,
                plan->num_envs);
   RS_CHECK_ARG(b->x && b->y && b->theta && b->goal_x && b->goal_y && b->step && b->episode,
@@ -351,6 +355,10 @@ rs_status rs_autotune(rs_ctx *ctx, const rs_params *p, const int32_t *robots, in
   if (s != RS_OK) return s;
   RS_CHECK_ARG(p->dtype == RS_F32 && action_driven(p->controller),
                "autotune runs the FP32 path of an action-driven controller");
+  if (p->scenario != RS_SCN_NAVIGATION) {
+    set_error("autotune runs the Navigation scenario");
+    return RS_ERR_UNSUPPORTED;
+  }
   for (int32_t k = 0; k < count; ++k)
     RS_CHECK_ARG(robots[k] >= 2 && robots[k] <= RS_MAX_ROBOTS, "robots[%d] = %d outside 2..16",
                  k, robots[k]);

@@ -91,7 +91,7 @@ __device__ __forceinline__ int perm_hidden(int s, int g, int j) {
 
 // NC > 0 fixes the robot count at compile time (NC <= G); NC = 0 reads it
 // from the arguments.
-template <int G, int NC>
+template <int G, int NC, bool PP>
 __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
   constexpr int EPW = 64 / G;
   __shared__ QPScratch<float, G> qs[kRollBlock / G];
@@ -342,7 +342,7 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
 
     // ---- 4. env step --------------------------------------------------------
     if (env_ok) {
-      const StepOut<float> so = env_step_group<float, G>(K, A.C.qp_cap, sh, lane, i, N, on, env_id,
+      const StepOut<float> so = env_step_group<float, G, PP>(K, A.C.qp_cap, sh, lane, i, N, on, env_id,
                                                          A.t0 + (uint32_t)t, action, x, y, th, c, s, gx, gy, step,
                                                          episode, false);
       if (i == 0) {
@@ -357,20 +357,24 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
 
 // Kernel for N robots: a compile-time robot count for N = 8 (8 lanes, no
 // idle lane), the lane-group width with a run-time count otherwise.
-static const void *rollout_kernel(int N) {
-  if (N == 8) return reinterpret_cast<const void *>(&k_rollout<8, 8>);
+template <bool PP> static const void *rollout_kernel_for(int N) {
+  if (N == 8) return reinterpret_cast<const void *>(&k_rollout<8, 8, PP>);
   switch (pow2_group(N)) {
-    case 2: return reinterpret_cast<const void *>(&k_rollout<2, 0>);
-    case 4: return reinterpret_cast<const void *>(&k_rollout<4, 0>);
-    case 8: return reinterpret_cast<const void *>(&k_rollout<8, 0>);
-    default: return reinterpret_cast<const void *>(&k_rollout<16, 0>);
+    case 2: return reinterpret_cast<const void *>(&k_rollout<2, 0, PP>);
+    case 4: return reinterpret_cast<const void *>(&k_rollout<4, 0, PP>);
+    case 8: return reinterpret_cast<const void *>(&k_rollout<8, 0, PP>);
+    default: return reinterpret_cast<const void *>(&k_rollout<16, 0, PP>);
   }
+}
+static const void *rollout_kernel(const RolloutArgs &A) {
+  return A.C.scenario == RS_SCN_PREDATOR_PREY ? rollout_kernel_for<true>(A.N)
+                                              : rollout_kernel_for<false>(A.N);
 }
 
 static bool launch_rollout(const RolloutArgs &A, dim3 grid, hipStream_t st) {
   RolloutArgs copy = A;
   void *kargs[] = {&copy};
-  return hipLaunchKernel(rollout_kernel(A.N), grid, dim3(kRollBlock), kargs, 0, st) == hipSuccess;
+  return hipLaunchKernel(rollout_kernel(A), grid, dim3(kRollBlock), kargs, 0, st) == hipSuccess;
 }
 
 }  // namespace rs
@@ -463,7 +467,7 @@ extern "C" rs_status rollout(rs_ctx *ctx, const rs_params *p, const rs_batch *b,
     void *kargs[] = {&copy};
     hipKernelNodeParams kp;
     std::memset(&kp, 0, sizeof(kp));
-    kp.func = const_cast<void *>(rollout_kernel(A.N));
+    kp.func = const_cast<void *>(rollout_kernel(A));
     kp.gridDim = grid;
     kp.blockDim = dim3(kRollBlock);
     kp.sharedMemBytes = 0;

@@ -101,8 +101,9 @@ __device__ void place_points(ConstRef<T> K, uint32_t env_id, uint32_t episode, u
 
 // Reset sampler for the group's environment (episode `episode`). Its
 // constants (lattice, separation, stream key) are loaded from the kernel
-// arguments where they are used: it is the cold path of a step.
-template <typename T, int G>
+// arguments where they are used: it is the cold path of a step. With PP
+// (Predator-Prey) every goal slot gets the prey: robot 0's goal point.
+template <typename T, int G, bool PP = false>
 __device__ void reset_env(ConstRef<T> K, uint32_t env_id, uint32_t episode, int i, int N,
                           int lane, T &x, T &y, T &th, T &gx, T &gy) {
   int64_t X, Y, GX, GY;
@@ -117,6 +118,43 @@ __device__ void reset_env(ConstRef<T> K, uint32_t env_id, uint32_t episode, int 
   y = (T)((double)Y * grid);
   gx = (T)((double)GX * grid);
   gy = (T)((double)GY * grid);
+  if constexpr (PP) {
+    const int base = lane & ~(G - 1);
+    gx = __shfl(gx, base, 64);
+    gy = __shfl(gy, base, 64);
+  }
+}
+
+// Predator-Prey prey move (appendix, Predator Prey: the prey keeps as far as
+// it can from the closest tagger). Candidates: stay, then a step of
+// prey_step in direction 2 pi k / 16 for k = 0..15, clamped to the walls
+// pulled in by r_s/2; the prey takes the candidate with the largest squared
+// distance to the closest robot centre (x, y of the calling lanes, before
+// they move), the first on ties. (qx, qy) is group-uniform in and out.
+template <typename T, int G, typename CS>
+__device__ __forceinline__ void prey_move(const CS &C, bool on, T x, T y, T &qx, T &qy) {
+  constexpr double kC = 0.92387953251128674, kH = 0.70710678118654752, kS = 0.38268343236508977;
+  constexpr double dir_c[16] = {1, kC, kH, kS, 0, -kS, -kH, -kC, -1, -kC, -kH, -kS, 0, kS, kH, kC};
+  constexpr double dir_s[16] = {0, kS, kH, kC, 1, kC, kH, kS, 0, -kS, -kH, -kC, -1, -kC, -kH, -kS};
+  const T far = T(1e30);
+  const T st = C.prey_step;
+  T dx = qx - x, dy = qy - y;
+  T best = gmin<G>(on ? dx * dx + dy * dy : far);
+  T bx = qx, by = qy;
+  static_for<0, 16>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    const T cx = tclamp(qx + st * T(dir_c[k]), C.xwl, C.xwh);
+    const T cy = tclamp(qy + st * T(dir_s[k]), C.ywl, C.ywh);
+    const T ex = cx - x, ey = cy - y;
+    const T sc = gmin<G>(on ? ex * ex + ey * ey : far);
+    if (sc > best) {
+      best = sc;
+      bx = cx;
+      by = cy;
+    }
+  });
+  qx = bx;
+  qy = by;
 }
 
 // Observation of robot i: x, y, cos th, sin th, (x_j - x_i, y_j - y_i) for
@@ -185,7 +223,7 @@ template <typename T> struct StepOut {
 // the step (keys the action noise). `step`/`episode` are group-uniform and
 // updated. Observation of the post-step state is left to the caller (c, s
 // are refreshed).
-template <typename T, int G>
+template <typename T, int G, bool PP = false>
 __device__ StepOut<T> env_step_group(ConstRef<T> K, int qp_cap, QPScratch<T, G> *sh, int lane,
                                      int i, int N, bool on, uint32_t env_id, uint32_t t, int action,
                                      T &x, T &y, T &th, T &c, T &s, T &gx, T &gy, int &step,
@@ -227,6 +265,15 @@ __device__ StepOut<T> env_step_group(ConstRef<T> K, int qp_cap, QPScratch<T, G> 
     uny += C.noise * (T(2) * unit24_t<T>(o.y) - T(1));
   }
   preclip(*K.get(), unx, uny);
+  // Predator-Prey: the prey (held in every goal slot) moves on the pre-step
+  // centres, at the same time as the robots
+  T qx = gx, qy = gy;
+  if constexpr (PP) {
+    const int base = lane & ~(G - 1);
+    qx = __shfl(gx, base, 64);
+    qy = __shfl(gy, base, 64);
+    prey_move<T, G>(*K.get(), on, x, y, qx, qy);
+  }
   T lox, hix, loy, hiy;
   wall_bounds(*K.get(), px, py, lox, hix, loy, hiy);
   T ux, uy;
@@ -240,20 +287,34 @@ __device__ StepOut<T> env_step_group(ConstRef<T> K, int qp_cap, QPScratch<T, G> 
   if (on) integrate(*K.get(), c, s, v, w, x, y, th);
   // reward and termination
   step += 1;
-  T dist = T(0);
-  if (on) {
-    const T ex = x - gx, ey = y - gy;
-    dist = sqrt_t(ex * ex + ey * ey);
-  }
-  out.reward = -gsum<G>(dist);
   const auto &Cd = *K.get();
-  const bool near_all = group_all<G>(!on || dist < Cd.goal_r, lane);
-  out.done = (Cd.goal_r > T(0) && near_all) || (Cd.max_steps > 0 && step >= Cd.max_steps);
+  if constexpr (PP) {
+    // tag: some centre closer than the tag radius to the moved prey
+    gx = qx;
+    gy = qy;
+    T dist = T(0);
+    if (on) {
+      const T ex = x - qx, ey = y - qy;
+      dist = sqrt_t(ex * ex + ey * ey);
+    }
+    const bool tag = group_any<G>(on && dist < Cd.tag_r, lane);
+    out.reward = tag ? Cd.tag_reward : T(0);
+    out.done = Cd.max_steps > 0 && step >= Cd.max_steps;
+  } else {
+    T dist = T(0);
+    if (on) {
+      const T ex = x - gx, ey = y - gy;
+      dist = sqrt_t(ex * ex + ey * ey);
+    }
+    out.reward = -gsum<G>(dist);
+    const bool near_all = group_all<G>(!on || dist < Cd.goal_r, lane);
+    out.done = (Cd.goal_r > T(0) && near_all) || (Cd.max_steps > 0 && step >= Cd.max_steps);
+  }
   if (out.done) {
     episode += 1;
     step = 0;
     T nx, ny, nth, ngx, ngy;
-    reset_env<T, G>(K, env_id, (uint32_t)episode, i, N, lane, nx, ny, nth, ngx, ngy);
+    reset_env<T, G, PP>(K, env_id, (uint32_t)episode, i, N, lane, nx, ny, nth, ngx, ngy);
     if (on) { x = nx; y = ny; th = nth; gx = ngx; gy = ngy; }
   }
   sincos_t(th, &s, &c);

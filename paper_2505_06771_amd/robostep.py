@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_PKG, "librobostep.so")
 
 RS_F32, RS_F64 = 0, 1
 RS_CTRL_DISCRETE, RS_CTRL_GOTO, RS_CTRL_WAYPOINT = 0, 1, 2
+RS_SCN_NAVIGATION, RS_SCN_PREDATOR_PREY = 0, 1
 STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "out of memory",
           4: "device error", 5: "over budget", 6: "not found"}
 
@@ -43,6 +44,8 @@ class RsParams(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("waypoint_step", ctypes.c_double), ("pos_gain", ctypes.c_double),
         ("ang_gain", ctypes.c_double), ("action_noise", ctypes.c_double),
+        ("prey_speed", ctypes.c_double), ("tag_radius", ctypes.c_double),
+        ("tag_reward", ctypes.c_double), ("scenario", ctypes.c_int32),
     ]
 
 

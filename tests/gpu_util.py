@@ -55,3 +55,32 @@ def oracle_state(b):
 def angle_diff(a, b):
     d = np.asarray(a, np.float64) - np.asarray(b, np.float64)
     return np.abs((d + math.pi) % (2 * math.pi) - math.pi)
+
+
+def prey_candidates(po, qx, qy):
+    """The prey's 17 candidate positions (stay, then 16 directions), rebuilt
+    from their definition for the band checks of the Predator-Prey tests."""
+    s = po.prey_speed * po.dt
+    lox, hix = po.x_min + po.safety_radius / 2, po.x_max - po.safety_radius / 2
+    loy, hiy = po.y_min + po.safety_radius / 2, po.y_max - po.safety_radius / 2
+    ang = 2 * math.pi * np.arange(16) / 16
+    cx = np.concatenate([[qx], np.clip(qx + s * np.cos(ang), lox, hix)])
+    cy = np.concatenate([[qy], np.clip(qy + s * np.sin(ang), loy, hiy)])
+    return cx, cy
+
+
+def prey_band(orc, po, x, y, qx, qy, gpu_qx, gpu_qy, tol=1e-5):
+    """True when the GPU's prey position is a candidate whose oracle score is
+    within `tol` (m^2) of the best one: a near-tie that FP32 rounding may
+    resolve either way."""
+    _, _, k, sc = orc.prey_move(po, x, y, qx, qy)
+    cx, cy = prey_candidates(po, qx, qy)
+    d = np.hypot(cx - gpu_qx, cy - gpu_qy)
+    j = int(np.argmin(d))
+    return d[j] <= 1e-5 and sc[k] - sc[j] <= tol
+
+
+def tag_band(po, x, y, qx, qy, tol=1e-5):
+    """True when some robot centre is within `tol` of the tag radius."""
+    d = np.hypot(np.asarray(x) - qx, np.asarray(y) - qy)
+    return bool((np.abs(d - po.tag_radius) < tol).any())

@@ -61,7 +61,8 @@ def test_params_struct_matches_oracle_constants(R):
     for f in ("x_min", "x_max", "dt", "proj_dist", "barrier_gain", "safety_radius",
               "boundary_gain_factor", "v_max", "action_speed", "kp", "wheel_radius",
               "base_length", "goal_radius", "reset_margin", "min_sep", "grid", "max_steps",
-              "waypoint_step", "pos_gain", "ang_gain", "action_noise"):
+              "waypoint_step", "pos_gain", "ang_gain", "action_noise", "prey_speed",
+              "tag_radius", "tag_reward", "scenario"):
         assert getattr(o, f) == getattr(p, f), f
 
 
@@ -70,7 +71,8 @@ def test_struct_layouts_match_the_header(R, tmp_path):
     import subprocess
 
     src = tmp_path / "sizes.c"
-    fields = {"rs_params": ["seed", "qp_max_iters", "grid", "waypoint_step", "action_noise"],
+    fields = {"rs_params": ["seed", "qp_max_iters", "grid", "waypoint_step", "action_noise",
+                            "tag_reward", "scenario"],
               "rs_batch": ["env_id_base", "episode"],
               "rs_policy": ["in_dim", "b3"], "rs_schedule": ["qp_iters", "lanes_per_env"],
               "rs_request_info": ["finish_time", "horizon"],
@@ -169,6 +171,9 @@ def test_params_check_covers_controllers_and_noise(R):
     assert ok(controller=R.RS_CTRL_WAYPOINT, waypoint_step=0.0) == 1
     assert b"waypoint_step" in L.rs_last_error()
     assert ok(action_noise=-0.1) == 1 and b"action_noise" in L.rs_last_error()
+    assert ok(scenario=R.RS_SCN_PREDATOR_PREY) == 0
+    assert ok(scenario=2) == 1 and b"scenario" in L.rs_last_error()
+    assert ok(scenario=R.RS_SCN_PREDATOR_PREY, prey_speed=-0.1) == 1
     assert ok(pos_gain=-1.0) == 1
     assert ok(dt=0.0) == 1
     assert ok() == 0 and L.rs_last_error() == b""

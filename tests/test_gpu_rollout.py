@@ -18,7 +18,8 @@ import numpy as np
 import pytest
 
 from paper_2505_06771_amd import synth
-from tests.gpu_util import angle_diff, banner, batch_from_states, ctx_and_lib, dev, host
+from tests.gpu_util import angle_diff, banner, batch_from_states, ctx_and_lib, dev, host, \
+    prey_band, tag_band
 
 pytestmark = pytest.mark.gpu
 
@@ -87,6 +88,8 @@ def run_and_check(orc, n, E, H, seed, sample_envs=None, sample_steps=None, step0
         stepc[t + 1] = np.where(dn[t] == 1, 0, stepc[t] + 1)
         epc[t + 1] = epc[t] + dn[t]
     nact, nband, worst = 0, 0, 0.0
+    pp = po.scenario == 1
+    npp_band = 0
     for t in steps:
         for e in envs:
             for i in range(n):
@@ -110,8 +113,26 @@ def run_and_check(orc, n, E, H, seed, sample_envs=None, sample_steps=None, step0
         for k, e in enumerate(envs):
             one = {kk: s[kk][k * n:(k + 1) * n].copy() for kk in ("x", "y", "th", "gx", "gy")}
             one["step"], one["episode"] = int(s["step"][k]), int(s["episode"][k])
+            pre = {kk: s[kk][k * n:(k + 1) * n].copy() for kk in ("x", "y", "gx", "gy")}
             out = orc.env_step(po, one, int(e), t0 + t, actions=acts[k * n:(k + 1) * n])
             assert out["status"] != 2
+            if pp:
+                # Predator-Prey: episodes end on the step limit only (exact); the
+                # prey's choice and the tag are compared outside their bands
+                assert out["done"] == dn[t, e], f"done t={t} e={e}"
+                nxt = ob[t + 1, e]
+                gq = (nxt[0, 0] + nxt[0, 2 * n + 2], nxt[0, 1] + nxt[0, 2 * n + 3])
+                if not out["done"] and max(abs(gq[0] - one["gx"][0]),
+                                           abs(gq[1] - one["gy"][0])) > 1e-5:
+                    assert prey_band(orc, po, pre["x"], pre["y"], pre["gx"][0], pre["gy"][0],
+                                     *gq), f"prey t={t} e={e}"
+                    npp_band += 1
+                    continue
+                if out["reward"] != rw[t, e]:
+                    assert tag_band(po, one["x"], one["y"], one["gx"][0], one["gy"][0]), \
+                        f"tag t={t} e={e}"
+                    npp_band += 1
+                    continue
             if out["done"] != dn[t, e]:
                 # band: some robot within 1e-5 m of the goal radius
                 free = {kk: s[kk][k * n:(k + 1) * n].copy() for kk in ("x", "y", "th", "gx", "gy")}
@@ -127,9 +148,23 @@ def run_and_check(orc, n, E, H, seed, sample_envs=None, sample_steps=None, step0
             assert d <= 1e-5, f"t={t} e={e}: pose gap {d}"
             assert abs(out["reward"] - rw[t, e]) <= n * 1e-5
             np.testing.assert_allclose(out["obs"], nxt, atol=1e-5, rtol=0)
-    print(f"rollout n={n}: actions {nact}, band mismatches {nband}, worst pose gap {worst:.3g}")
+    print(f"rollout n={n}: actions {nact}, band mismatches {nband}, worst pose gap {worst:.3g}"
+          f", prey/tag band cases {npp_band}")
     assert nband <= max(2, 0.005 * nact)
+    assert npp_band <= max(2, 0.005 * nact / n)
     return b, ob, ac, rw, dn
+
+
+@pytest.mark.parametrize("n", [3, 8])
+def test_rollout_predator_prey(orc, n):
+    """Predator-Prey rollout with waypoint actions: the prey's flight, the tag
+    reward and the 100-step episodes inside the fused kernel."""
+    E = {3: 90, 8: 131}[n]
+    rng = np.random.default_rng(70 + n)
+    step0 = rng.integers(70, 100, E).astype(np.int32)
+    _, _, _, rw, dn = run_and_check(orc, n, E, H=40, seed=80 + n, step0=step0,
+                                    extra=dict(scenario=1, controller=2, max_steps=100))
+    assert dn.sum() >= E // 2
 
 
 @pytest.mark.parametrize("n", [4, 8])
