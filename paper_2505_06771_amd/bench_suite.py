@@ -12,6 +12,9 @@
                    actions (unicycle position controller) and action noise,
                    beside the same rollout with discrete moves and no noise
                    (kernel ms per launch from HIP events, robot-steps/s)
+  rollout_predator_prey
+                   Predator-Prey rollouts (waypoint actions, 100-step
+                   episodes): 16384 envs x 8 robots and 43690 envs x 3
   serving          Poisson rollout requests (64-4096 envs log-uniform, N in
                    3..16, horizon 50-500): continuous batching vs plain
                    per-request per-step launches; p50/p99 latency + robot-steps/s
@@ -276,7 +279,9 @@ def serving(R, ctx, seed=0, count=600, skip=60, budget=16 << 30, tick=32, rate=N
             "plain_robot_steps_per_s": work_p / wall_p}
 
 
-def rollout_waypoint_noise(R, ctx, seed=0, launches=10, E=16384, n=8, H=128, sigma=0.05):
+def _time_rollout(R, ctx, p, E, n, H, launches, seed):
+    """Median kernel time (ms, HIP events on the launch stream) of `launches`
+    rollout launches after two warm-ups, from a fresh reset."""
     import torch
 
     from paper_2505_06771_amd import synth
@@ -291,29 +296,37 @@ def rollout_waypoint_noise(R, ctx, seed=0, launches=10, E=16384, n=8, H=128, sig
     rew = torch.empty(H * E, device="cuda")
     done = torch.empty(H * E, dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
-    # HBM bytes per launch: obs + action per robot-step, reward + done per
-    # env-step, state in and out once, weights once
-    algo = (H * (E * n * (4 * D + 1) + E * 5) + 2 * (E * n * 20 + E * 8)
+    b = R.Batch.empty(E, n)
+    R.env_reset(ctx, p, b)
+    for k in range(2):
+        R.rollout(ctx, p, b, pol, H, k * H, obs, act, rew, done, stream=stream)
+    _sync()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(launches)]
+    for k in range(launches):
+        ev[k][0].record(stream)
+        R.rollout(ctx, p, b, pol, H, (2 + k) * H, obs, act, rew, done, stream=stream)
+        ev[k][1].record(stream)
+    _sync()
+    ms = sorted(a.elapsed_time(z) for a, z in ev)
+    return ms[len(ms) // 2], float(rew.sum().item())
+
+
+def _rollout_bytes(E, n, H):
+    """HBM bytes per launch: obs + action per robot-step, reward + done per
+    env-step, state in and out once, weights once."""
+    D = 2 * n + 4
+    return (H * (E * n * (4 * D + 1) + E * 5) + 2 * (E * n * 20 + E * 8)
             + 2 * (D * 64 + 64 * 64 + 64 * 5) + 4 * (64 + 64 + 5))
+
+
+def rollout_waypoint_noise(R, ctx, seed=0, launches=10, E=16384, n=8, H=128, sigma=0.05):
+    algo = _rollout_bytes(E, n, H)
     res = {"config": "rollout_waypoint_noise", "envs": E, "robots": n, "horizon": H,
            "launches": launches, "action_noise": sigma}
     for name, kw in (("discrete", {}),
                      ("waypoint_noise", {"controller": R.RS_CTRL_WAYPOINT, "action_noise": sigma})):
-        p = R.params(seed=seed, **kw)
-        b = R.Batch.empty(E, n)
-        R.env_reset(ctx, p, b)
-        for k in range(2):
-            R.rollout(ctx, p, b, pol, H, k * H, obs, act, rew, done, stream=stream)
-        _sync()
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(launches)]
-        for k in range(launches):
-            ev[k][0].record(stream)
-            R.rollout(ctx, p, b, pol, H, (2 + k) * H, obs, act, rew, done, stream=stream)
-            ev[k][1].record(stream)
-        _sync()
-        ms = sorted(a.elapsed_time(z) for a, z in ev)
-        med = ms[len(ms) // 2]
+        med, _ = _time_rollout(R, ctx, R.params(seed=seed, **kw), E, n, H, launches, seed)
         res[f"kernel_ms_median_{name}"] = med
         res[f"robot_steps_per_s_{name}"] = E * n * H / (med * 1e-3)
         res[f"hbm_frac_{name}"] = algo / (med * 1e-3) / 8e12
@@ -321,8 +334,27 @@ def rollout_waypoint_noise(R, ctx, seed=0, launches=10, E=16384, n=8, H=128, sig
     return res
 
 
+def rollout_predator_prey(R, ctx, seed=0, launches=10, H=128):
+    """Predator-Prey rollouts with waypoint actions and 100-step episodes: the
+    headline shape (16384 envs x 8 robots) and the paper's team size (3
+    robots) on the same number of robots."""
+    res = {"config": "rollout_predator_prey", "horizon": H, "launches": launches,
+           "controller": "waypoint", "max_steps": 100}
+    for E, n in ((16384, 8), (43690, 3)):
+        p = R.params(seed=seed, scenario=R.RS_SCN_PREDATOR_PREY,
+                     controller=R.RS_CTRL_WAYPOINT, max_steps=100)
+        med, tags = _time_rollout(R, ctx, p, E, n, H, launches, seed)
+        algo = _rollout_bytes(E, n, H)
+        key = f"{E}x{n}"
+        res[f"kernel_ms_median_{key}"] = med
+        res[f"robot_steps_per_s_{key}"] = E * n * H / (med * 1e-3)
+        res[f"hbm_frac_{key}"] = algo / (med * 1e-3) / 8e12
+        res[f"tag_reward_last_launch_{key}"] = tags
+    return res
+
+
 def run_all(path, seed=0, which=("single_env_f64", "uniform_4096x4", "uneven_8192",
-                                 "rollout_waypoint_noise", "serving")):
+                                 "rollout_waypoint_noise", "rollout_predator_prey", "serving")):
     import os
 
     import torch
@@ -334,7 +366,7 @@ def run_all(path, seed=0, which=("single_env_f64", "uniform_4096x4", "uneven_819
     os.makedirs(os.path.dirname(path), exist_ok=True)
     fns = {"single_env_f64": single_env_f64, "uniform_4096x4": uniform_4096x4,
            "uneven_8192": uneven_8192, "rollout_waypoint_noise": rollout_waypoint_noise,
-           "serving": serving}
+           "rollout_predator_prey": rollout_predator_prey, "serving": serving}
     with open(path, "w") as f:
         for name in which:
             _log(f"[suite] {name} ...")
@@ -354,4 +386,4 @@ if __name__ == "__main__":
     a = ap.parse_args()
     run_all(a.out, which=tuple(a.only) if a.only else
             ("single_env_f64", "uniform_4096x4", "uneven_8192", "rollout_waypoint_noise",
-             "serving"))
+             "rollout_predator_prey", "serving"))
