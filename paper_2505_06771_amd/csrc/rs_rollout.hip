@@ -237,6 +237,15 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
     }
 
     // ---- 2. policy MLP on MFMA, one tile of 16 robots at a time ----------
+    // hidden biases (accumulator seeds): read once per step, shared by the
+    // four tiles
+    floatx4 b1v[4], b2v[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      const float4 p1 = bias_lds[0][mt][g], p2 = bias_lds[1][mt][g];
+      b1v[mt] = (floatx4){p1.x, p1.y, p1.z, p1.w};
+      b2v[mt] = (floatx4){p2.x, p2.y, p2.z, p2.w};
+    }
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
       const int n = 16 * nt + c16;  // wave lane of the robot in this column
@@ -266,20 +275,15 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
       }
       floatx4 h1[4];
 #pragma unroll
-      for (int mt = 0; mt < 4; ++mt) {
-        const float4 bb = bias_lds[0][mt][g];
-        const floatx4 b1v = {bb.x, bb.y, bb.z, bb.w};
-        h1[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1f[mt], xb, b1v, 0, 0, 0);
-      }
+      for (int mt = 0; mt < 4; ++mt)
+        h1[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1f[mt], xb, b1v[mt], 0, 0, 0);
       bf16x8 hb[2];
 #pragma unroll
       for (int sk = 0; sk < 2; ++sk) hb[sk] = pack_bf16x8<true>(h1[2 * sk], h1[2 * sk + 1]);
       floatx4 h2[4];
 #pragma unroll
       for (int mo = 0; mo < 4; ++mo) {
-        const float4 bb = bias_lds[1][mo][g];
-        const floatx4 b2v = {bb.x, bb.y, bb.z, bb.w};
-        h2[mo] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2f[mo][0], hb[0], b2v, 0, 0, 0);
+        h2[mo] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2f[mo][0], hb[0], b2v[mo], 0, 0, 0);
         h2[mo] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2f[mo][1], hb[1], h2[mo], 0, 0, 0);
       }
       bf16x8 hc[2];
