@@ -885,7 +885,7 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
 
   // --- geometry of the owned pairs and their violations at u0 ---------------
   // (the partner's position and command are fetched together)
-  T cdx[KH], cdy[KH], cb[KH], crn[KH], snk[KH];
+  T cdx[KH], cdy[KH], cb[KH], snk[KH];
   int cpid[KH];
   bool coincide = false;
   static_for<1, KH + 1>([&](auto kc) {
@@ -894,9 +894,11 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
     const T uxj = grot<G, K>(ux, lane), uyj = grot<G, K>(uy, lane);
     const int j = (i + K) & (G - 1);
     const bool valid = on && j < N && !(2 * K == G && i >= KH);
-    const bool ia = i < j;
-    const T dx = ia ? px - pxj : pxj - px;
-    const T dy = ia ? py - pyj : pyj - py;
+    // D = p_i - p_j as this lane sees the pair. The row's own D runs from
+    // its lower-index robot, which only flips the sign: the distance, the
+    // pruning test and the violation do not see it, and it is applied when
+    // the row is picked.
+    const T dx = px - pxj, dy = py - pyj;
     const T d2 = dx * dx + dy * dy;
     const T h = d2 - C.rs2;
     const T bb = C.gamma * (h * h * h);
@@ -904,12 +906,12 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
     cdx[K - 1] = dx;
     cdy[K - 1] = dy;
     cb[K - 1] = bb;
-    crn[K - 1] = d2 > T(0) ? T(0.35355339059327373) * rsqrt_t(d2) : T(0);
-    cpid[K - 1] = (cand && d2 > T(0)) ? ((ia ? i : j) << 4 | (ia ? j : i)) : -1;
+    cpid[K - 1] = (cand && d2 > T(0)) ? (min(i, j) << 4 | max(i, j)) : -1;
     if (cand && !(d2 > T(0)) && bb < T(0)) coincide = true;
-    const T dux = ia ? uxj - ux : ux - uxj;
-    const T duy = ia ? uyj - uy : uy - uyj;
-    const T sn = (T(2) * (dx * dux + dy * duy) - bb) * crn[K - 1];
+    // violation 2 D.(u_j - u_i) - b over |c| = 2 sqrt(2) |D| (a pair with
+    // D = 0 is no candidate: its value is never used)
+    const T sn = (T(2) * (dx * (uxj - ux) + dy * (uyj - uy)) - bb) *
+                 (T(0.35355339059327373) * rsqrt_t(d2));
     snk[K - 1] = cpid[K - 1] >= 0 ? sn : -BIG;
   });
   bool dead = group_any<G>(coincide || (on && (lox > hix || loy > hiy)), lane);
@@ -964,6 +966,10 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
       bdx = __shfl(bdx, src, 64);
       bdy = __shfl(bdy, src, 64);
       bbb = __shfl(bbb, src, 64);
+      // orient D from the row's lower-index robot (the owner is either end)
+      const bool flip = wl != (bid >> 4);
+      bdx = flip ? -bdx : bdx;
+      bdy = flip ? -bdy : bdy;
     }
     if (bid < 0) {
       run_gi = false;  // u0 is the solution
@@ -988,6 +994,9 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
         e2x = __shfl(e2x, src, 64);
         e2y = __shfl(e2y, src, 64);
         beta2 = __shfl(beta2, src, 64);
+        const bool flip2 = w2 != (id2 >> 4);
+        e2x = flip2 ? -e2x : e2x;
+        e2y = flip2 ? -e2y : e2y;
       }
       const bool two = nv == 2 && id2 >= 0;
       const int pa = bid >> 4, pb = bid & 15;
