@@ -26,9 +26,12 @@ template <> __device__ __forceinline__ double pi_v<double>() { return kPiD; }
 // error (~1e-6) is far inside the tolerances of positions and observations.
 __device__ __forceinline__ void sincos_t(float a, float *s, float *c) { __sincosf(a, s, c); }
 __device__ __forceinline__ void sincos_t(double a, double *s, double *c) { sincos(a, s, c); }
-__device__ __forceinline__ float sqrt_t(float a) { return sqrtf(a); }
+// FP32 square root and reciprocal square root as the hardware instructions
+// (about 1 ulp; no rescaling for denormal inputs, which the simulation's
+// squared distances and speeds never are)
+__device__ __forceinline__ float sqrt_t(float a) { return __builtin_amdgcn_sqrtf(a); }
 __device__ __forceinline__ double sqrt_t(double a) { return sqrt(a); }
-__device__ __forceinline__ float rsqrt_t(float a) { return rsqrtf(a); }
+__device__ __forceinline__ float rsqrt_t(float a) { return __builtin_amdgcn_rsqf(a); }
 __device__ __forceinline__ double rsqrt_t(double a) { return rsqrt(a); }
 
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32 multiplies

@@ -19,12 +19,13 @@ __device__ __forceinline__ int drawn_action(uint32_t k0, uint32_t k1, uint32_t e
   return (int)(((uint64_t)word(o, i & 3) * 5ull) >> 32);
 }
 
-// Magnitude limit of the nominal command.
+// Magnitude limit of the nominal command, decided on squared norms (an
+// axis-aligned command of exactly v_max squares to v_max^2 and is left alone).
 template <typename T, typename CS>
 __device__ __forceinline__ void preclip(const CS &C, T &ux, T &uy) {
-  const T nrm = sqrt_t(ux * ux + uy * uy);
-  if (nrm > C.vmax) {
-    const T sc = C.vmax / nrm;
+  const T n2 = ux * ux + uy * uy;
+  if (n2 > C.vmax * C.vmax) {
+    const T sc = C.vmax * rsqrt_t(n2);
     ux *= sc;
     uy *= sc;
   }
