@@ -58,7 +58,8 @@ __device__ __forceinline__ uint4 stream_block(uint32_t k0, uint32_t k1, uint32_t
 }
 
 __device__ __forceinline__ uint32_t word(uint4 v, int k) {
-  return k == 0 ? v.x : (k == 1 ? v.y : (k == 2 ? v.z : v.w));
+  const uint32_t lo = (k & 1) ? v.y : v.x, hi = (k & 1) ? v.w : v.z;
+  return (k & 2) ? hi : lo;
 }
 
 // 24-bit uniform in [0, 1): exact in FP32 (and in FP64).

@@ -305,9 +305,10 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
     float mx = l5[0];
 #pragma unroll
     for (int k = 1; k < 5; ++k) mx = fmaxf(mx, l5[k]);
-    float ex[5], tot = 0.f;
+    float ex[5];
 #pragma unroll
-    for (int k = 0; k < 5; ++k) { ex[k] = __expf(l5[k] - mx); tot += ex[k]; }
+    for (int k = 0; k < 5; ++k) ex[k] = __expf(l5[k] - mx);
+    const float tot = (((ex[0] + ex[1]) + ex[2]) + ex[3]) + ex[4];
     const uint32_t env_id = A.env_base + (uint32_t)e;
     // Sampling word of robot i at stream time t0 + t: word i&3 of block
     // (env_id, t0 + t, 1<<24 | i>>2, 0). With G >= 4 a lane quad holds the 4
@@ -335,13 +336,16 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
                                 (uint32_t)(i >> 2), 0u), i & 3);
     }
     const float u = unit24(rbits);
-    int action = 4;
-    float cdf = 0.f;
+    // first k with u < C_k (C the cumulative distribution), else 4: the
+    // cumulative sums do not decrease, so that is the number of k < 4 with
+    // C_k <= u
     const float inv_tot = __builtin_amdgcn_rcpf(tot);
+    float cdf = ex[0] * inv_tot;
+    int action = u < cdf ? 0 : 1;
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
+    for (int k = 1; k < 4; ++k) {
       cdf += ex[k] * inv_tot;
-      if (action == 4 && k < 4 && u < cdf) action = k;
+      action += u < cdf ? 0 : 1;
     }
     // per-step base pointers are uniform; the lane offsets are 32-bit
     uint8_t *act_t = A.actions + (size_t)t * (size_t)A.E * (size_t)N;
