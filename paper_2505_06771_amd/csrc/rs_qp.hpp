@@ -885,7 +885,7 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
 
   // --- geometry of the owned pairs and their violations at u0 ---------------
   // (the partner's position and command are fetched together)
-  T cdx[KH], cdy[KH], cb[KH], snk[KH];
+  T cdx[KH], cdy[KH], cb[KH], crn[KH], snk[KH];
   int cpid[KH];
   bool coincide = false;
   static_for<1, KH + 1>([&](auto kc) {
@@ -910,8 +910,8 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
     if (cand && !(d2 > T(0)) && bb < T(0)) coincide = true;
     // violation 2 D.(u_j - u_i) - b over |c| = 2 sqrt(2) |D| (a pair with
     // D = 0 is no candidate: its value is never used)
-    const T sn = (T(2) * (dx * (uxj - ux) + dy * (uyj - uy)) - bb) *
-                 (T(0.35355339059327373) * rsqrt_t(d2));
+    crn[K - 1] = T(0.35355339059327373) * rsqrt_t(d2);
+    const T sn = (T(2) * (dx * (uxj - ux) + dy * (uyj - uy)) - bb) * crn[K - 1];
     snk[K - 1] = cpid[K - 1] >= 0 ? sn : -BIG;
   });
   bool dead = group_any<G>(coincide || (on && (lox > hix || loy > hiy)), lane);
@@ -1110,26 +1110,20 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
         const bool out = mv && (vx < lox || vx > hix || vy < loy || vy > hiy);
         ok = ok && !group_any<G>(out, lane);
       }
-      // check every row through a moved robot, except the guessed ones (the
-      // second row's robots only when some group of the wavefront has one)
-      const int mr[4] = {pa, pb, qa, qb};
-      const bool any_two = __ballot(two) != 0;
+      // check every candidate row at the guess, except the guessed ones, from
+      // the geometry of the scan: a row with both ends unmoved keeps its value
+      // at u0 (below the threshold), and a pruned row holds anywhere in the
+      // speed box, which contains every guess
       bool bad = !ok;
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        if (m >= 2 && !any_two) break;
-        const int x = mr[m], lx = gbase + x;
-        const T pxx = __shfl(px, lx, 64), pyx = __shfl(py, lx, 64);
-        const T uxx = __shfl(nux, lx, 64), uyx = __shfl(nuy, lx, 64);
-        const bool guessed = (x == pa && i == pb) || (x == pb && i == pa) ||
-                             (two && ((x == qa && i == qb) || (x == qb && i == qa)));
-        const T dx = pxx - px, dy = pyx - py;
-        const T d2 = dx * dx + dy * dy;
-        const T h = d2 - C.rs2;
-        T sn = T(2) * (dx * (nux - uxx) + dy * (nuy - uyx)) - C.gamma * (h * h * h);
-        sn = d2 > T(0) ? sn * (T(0.35355339059327373) * rsqrt_t(d2)) : sn;
-        bad = bad || (on && x != i && !guessed && sn > C.tol_add);
-      }
+      static_for<1, KH + 1>([&](auto kc) {
+        constexpr int K = decltype(kc)::value;
+        const T uxj = grot<G, K>(nux, lane), uyj = grot<G, K>(nuy, lane);
+        const int id = cpid[K - 1];
+        const bool guessed = (id == bid) | (two & (id == id2));
+        const T sn = (T(2) * (cdx[K - 1] * (uxj - nux) + cdy[K - 1] * (uyj - nuy)) - cb[K - 1]) *
+                     crn[K - 1];
+        bad = bad | ((id >= 0) & !guessed & (sn > C.tol_add));
+      });
       const bool accept = !group_any<G>(bad, lane);
       // accepted: the guess is the solution; one rejected row with ok: start
       // the loop from u(l) with p active; otherwise from u0 (unchanged)
