@@ -1037,10 +1037,14 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
           for (int k = 0; k < 4; ++k) acc += cc[k] * tclamp(un[k] - lm * cc[k], lo[k], hi[k]);
           return acc;
         };
-        // largest breakpoint (or 0) where phi is still positive; the eight
-        // breakpoints are shared out over the group's lanes and the best one
-        // found by a butterfly (equal breakpoints give equal phi)
+        // the root lies between the largest breakpoint (or 0) where phi is
+        // still positive, (llo, plo), and the smallest one where it is not,
+        // (lhi, phi_hi): no breakpoint falls in between, so phi is linear
+        // there. The eight breakpoints are shared out over the group's lanes
+        // and both ends found by one butterfly (equal breakpoints give equal
+        // phi). No breakpoint with phi <= 0: the row cannot be met in the box.
         T llo = T(0), plo = phi(T(0));
+        T lhi = BIG, phh = T(0);
         {
           T bl = T(-1), bv = T(0);
           for (int b = i; b < 8; b += G) {
@@ -1048,9 +1052,13 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
             const T ek = (b & 1) ? (k == 0 ? e2[0] : k == 1 ? e2[1] : k == 2 ? e2[2] : e2[3])
                                  : (k == 0 ? e1[0] : k == 1 ? e1[1] : k == 2 ? e1[2] : e1[3]);
             const T pk = phi(ek);
-            const bool better = pk > T(0) && ek > bl;
+            const bool pos = pk > T(0);
+            const bool better = pos & (ek > bl);
             bl = better ? ek : bl;
             bv = better ? pk : bv;
+            const bool upper = !pos & (ek < lhi);
+            lhi = upper ? ek : lhi;
+            phh = upper ? pk : phh;
           }
           auto merge = [&](auto c) {
             constexpr int CT = decltype(c)::value;
@@ -1058,6 +1066,10 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
             const bool better = w > bl;
             bl = better ? w : bl;
             bv = better ? q : bv;
+            const T wu = dpp<CT>(lhi), qu = dpp<CT>(phh);
+            const bool lower = wu < lhi;
+            lhi = lower ? wu : lhi;
+            phh = lower ? qu : phh;
           };
           merge(std::integral_constant<int, 0xB1>{});
           if constexpr (G >= 4) merge(std::integral_constant<int, 0x4E>{});
@@ -1066,15 +1078,8 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
           plo = bl > llo ? bv : plo;
           llo = bl > llo ? bl : llo;
         }
-        // slope of -phi just right of llo: coordinates still free there
-        T slope = T(0);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const bool fr = cc[k] != T(0) && tmin(e1[k], e2[k]) <= llo && llo < tmax(e1[k], e2[k]);
-          slope += fr ? cc[k] * cc[k] : T(0);
-        }
-        ok = ok && (!use || slope > T(0));
-        const T lam = tmax(llo + qdiv(plo, tmax(slope, T(1e-30))), T(0));
+        ok = ok && (!use || lhi < BIG);
+        const T lam = llo + plo * (tmin(lhi, BIG) - llo) * qdiv(T(1), plo - phh);
         const bool ma = use && i == ra, mb = use && i == rb;
         const T ax = tclamp(un[0] - lam * cc[0], lo[0], hi[0]);
         const T ay = tclamp(un[1] - lam * cc[1], lo[1], hi[1]);
