@@ -1024,13 +1024,6 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
                          __shfl(loy, lb, 64)};
         const T hi[4] = {__shfl(hix, la, 64), __shfl(hiy, la, 64), __shfl(hix, lb, 64),
                          __shfl(hiy, lb, 64)};
-        T e1[4], e2[4];  // multiplier values where coordinate k meets hi_k / lo_k
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const T r = cc[k] != T(0) ? qdiv(T(1), cc[k]) : T(0);
-          e1[k] = (un[k] - hi[k]) * r;
-          e2[k] = (un[k] - lo[k]) * r;
-        }
         auto phi = [&](T lm) {
           T acc = -beta;
 #pragma unroll
@@ -1048,9 +1041,16 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
         {
           T bl = T(-1), bv = T(0);
           for (int b = i; b < 8; b += G) {
+            // breakpoint b: the multiplier where coordinate k = b / 2 meets
+            // its upper (b even) or lower (b odd) bound; a coordinate the row
+            // does not move gives 0
             const int k = b >> 1;
-            const T ek = (b & 1) ? (k == 0 ? e2[0] : k == 1 ? e2[1] : k == 2 ? e2[2] : e2[3])
-                                 : (k == 0 ? e1[0] : k == 1 ? e1[1] : k == 2 ? e1[2] : e1[3]);
+            auto pick = [&](const T *v) {
+              const T lo2 = (k & 1) ? v[1] : v[0], hi2 = (k & 1) ? v[3] : v[2];
+              return (k & 2) ? hi2 : lo2;
+            };
+            const T ck = pick(cc), uk = pick(un), bk = (b & 1) ? pick(lo) : pick(hi);
+            const T ek = ck != T(0) ? (uk - bk) * qdiv(T(1), ck) : T(0);
             const T pk = phi(ek);
             const bool pos = pk > T(0);
             const bool better = pos & (ek > bl);
