@@ -96,10 +96,10 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
   constexpr int EPW = 64 / G;
   __shared__ QPScratch<float, G> qs[kRollBlock / G];
   __shared__ __attribute__((aligned(16))) float obs_lds[kRollWaves][64 * 32];
-  // logits 4g..4g+3 of every robot, g = 0..3 (g >= 2: the padding rows of
-  // the last layer, never read; written so that the four tiles of the MLP
-  // are one branch-free block the scheduler can interleave)
-  __shared__ float4 logit_lds[kRollWaves][64 * 4];
+  // logits 4g..4g+3 of robot n at [g][n], g = 0..3 (g >= 2: the padding
+  // rows of the last layer, never read; written so that the four tiles of
+  // the MLP are one branch-free block the scheduler can interleave)
+  __shared__ float4 logit_lds[kRollWaves][4 * 64];
   // hidden-layer biases in the accumulator layout: [layer][tile][lane group]
   __shared__ float4 bias_lds[2][4][4];
 
@@ -295,12 +295,12 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
       floatx4 lg = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3f[0], hc[0], b3f, 0, 0, 0);
       lg = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3f[1], hc[1], lg, 0, 0, 0);
       // lane (g, c16) holds logits 4g..4g+3 of robot n
-      logit_w[n * 4 + g] = make_float4(lg[0], lg[1], lg[2], lg[3]);
+      logit_w[g * 64 + n] = make_float4(lg[0], lg[1], lg[2], lg[3]);
     }
     wave_lds_sync();
 
     // ---- 3. categorical draw in the robot's own lane ----------------------
-    const float4 la = logit_w[lane * 4], lb = logit_w[lane * 4 + 1];
+    const float4 la = logit_w[lane], lb = logit_w[64 + lane];
     const float l5[5] = {la.x, la.y, la.z, la.w, lb.x};
     float mx = l5[0];
 #pragma unroll
