@@ -416,7 +416,7 @@ namespace rs {
 // When a row must enter while all slots are taken, or the Gram system loses
 // positive definiteness, the general solver restarts from scratch.
 // ---------------------------------------------------------------------------
-constexpr int kQR = 3;
+constexpr int kQR = 4;
 
 template <typename T> struct QPActive {
   int q;
