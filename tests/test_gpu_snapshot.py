@@ -21,15 +21,20 @@ def _run(R, ctx, p, b, t0, t1, rewards):
         rewards.append((host(rew).copy(), host(done).copy()))
 
 
-@pytest.mark.parametrize("prec", ["f32", "f64"])
-def test_resume_is_bit_identical(prec):
+@pytest.mark.parametrize("prec,extra", [
+    ("f32", {}), ("f64", {}),
+    # Predator-Prey with waypoints and action noise: the prey lives in the goal
+    # slots and the noise is keyed by the stream time, so the same arrays resume it
+    ("f32", {"scenario": 1, "controller": 2, "action_noise": 0.05}),
+], ids=["f32", "f64", "f32-predator-prey"])
+def test_resume_is_bit_identical(prec, extra):
     import torch
 
     R, ctx = ctx_and_lib()
     dt = torch.float32 if prec == "f32" else torch.float64
     E, n = 64, 4
-    p = R.params(seed=11, dtype=R.RS_F32 if prec == "f32" else R.RS_F64, max_steps=300)
-    banner(f"snapshot {prec} E={E} n={n}")
+    p = R.params(seed=11, dtype=R.RS_F32 if prec == "f32" else R.RS_F64, max_steps=300, **extra)
+    banner(f"snapshot {prec} E={E} n={n} {extra}")
     a = R.Batch.empty(E, n, dtype=dt)
     R.env_reset(ctx, p, a)
     b = R.Batch.empty(E, n, dtype=dt)
