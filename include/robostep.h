@@ -275,8 +275,8 @@ rs_status env_reset_mixed(rs_ctx *ctx, const rs_params *p, const rs_plan *plan,
 
 /* ---------------------------------------------------------------------------
  * env_run -- `steps` consecutive env_step calls with drawn actions for a mixed
- * batch in ONE persistent launch (FP32, Navigation scenario; RS_CTRL_DISCRETE
- * or RS_CTRL_WAYPOINT, action noise as set). Env e runs
+ * batch in ONE persistent launch (FP32; RS_CTRL_DISCRETE or RS_CTRL_WAYPOINT,
+ * action noise and scenario as set). Env e runs
  * steps_per_env ? min(steps, steps_per_env[e]) : steps steps, with stream time
  * t_start[e] + k (t_start NULL: t_global0 + k) at its k-th step. Outputs (each
  * may be NULL): reward_out/done_out [steps][E] (rows past an env's own count

@@ -25,7 +25,7 @@ constexpr int kMaxWaveLds =
     std::max(std::max(qp_bytes_per_wave<2>(), qp_bytes_per_wave<4>()),
              std::max(qp_bytes_per_wave<8>(), qp_bytes_per_wave<16>()));
 
-template <int G>
+template <int G, bool PP>
 __device__ void run_tile(const RunArgs &A, char *wave_lds, int lane, int first, int count) {
   QPScratch<float, G> *sh = reinterpret_cast<QPScratch<float, G> *>(wave_lds) + lane / G;
   const int i = lane & (G - 1);
@@ -42,7 +42,7 @@ __device__ void run_tile(const RunArgs &A, char *wave_lds, int lane, int first, 
   float x = 0.f, y = 0.f, th = 0.f, gx = 0.f, gy = 0.f;
   int step = A.step[e], episode = A.episode[e];
   if (A.reset_mask && A.reset_mask[e]) {
-    reset_env<float, G>(K, env_id, (uint32_t)episode, i, N, lane, x, y, th, gx, gy);
+    reset_env<float, G, PP>(K, env_id, (uint32_t)episode, i, N, lane, x, y, th, gx, gy);
     step = 0;
     if (i == 0) A.reset_mask[e] = 0;
   } else if (on) {
@@ -60,7 +60,7 @@ __device__ void run_tile(const RunArgs &A, char *wave_lds, int lane, int first, 
   for (int k = 0; k < nsteps; ++k) {
     const auto *P = K.get();
     const int action = drawn_action(P->key0, P->key1, env_id, (uint32_t)(tb + k), i);
-    const StepOut<float> so = env_step_group<float, G>(K, qp_cap, sh, lane, i, N, on, env_id,
+    const StepOut<float> so = env_step_group<float, G, PP>(K, qp_cap, sh, lane, i, N, on, env_id,
                                                        (uint32_t)(tb + k), action, x, y, th, c, s, gx, gy, step,
                                                        episode, false);
     rsum += so.reward;
@@ -82,6 +82,9 @@ __device__ void run_tile(const RunArgs &A, char *wave_lds, int lane, int first, 
   }
 }
 
+// PP: the Predator-Prey scenario (prey in the goal slots), a separate
+// specialisation so that the Navigation kernel carries none of its code.
+template <bool PP>
 __global__ __launch_bounds__(256) void k_env_run(RunArgs A) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -90,10 +93,10 @@ __global__ __launch_bounds__(256) void k_env_run(RunArgs A) {
   const int4 td = A.tiles[tile];
   char *mine = lds + (size_t)wave * kMaxWaveLds;
   switch (td.x) {
-    case 2: run_tile<2>(A, mine, lane, td.y, td.z); break;
-    case 4: run_tile<4>(A, mine, lane, td.y, td.z); break;
-    case 8: run_tile<8>(A, mine, lane, td.y, td.z); break;
-    default: run_tile<16>(A, mine, lane, td.y, td.z); break;
+    case 2: run_tile<2, PP>(A, mine, lane, td.y, td.z); break;
+    case 4: run_tile<4, PP>(A, mine, lane, td.y, td.z); break;
+    case 8: run_tile<8, PP>(A, mine, lane, td.y, td.z); break;
+    default: run_tile<16, PP>(A, mine, lane, td.y, td.z); break;
   }
 }
 
@@ -101,7 +104,12 @@ hipError_t launch_run(const RunArgs &A, int block_threads, hipStream_t st) {
   const int waves = block_threads / 64;
   const int blocks = (A.num_tiles + waves - 1) / waves;
   if (blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_env_run, dim3(blocks), dim3(block_threads), waves * kMaxWaveLds, st, A);
+  if (A.C.scenario == RS_SCN_PREDATOR_PREY)
+    hipLaunchKernelGGL(k_env_run<true>, dim3(blocks), dim3(block_threads), waves * kMaxWaveLds, st,
+                       A);
+  else
+    hipLaunchKernelGGL(k_env_run<false>, dim3(blocks), dim3(block_threads), waves * kMaxWaveLds, st,
+                       A);
   return hipGetLastError();
 }
 
@@ -188,10 +196,6 @@ static rs_status check_mixed(const rs_ctx *ctx, const rs_params *p, const rs_pla
   if (s != RS_OK) return s;
   RS_CHECK_ARG(p->dtype == RS_F32, "mixed batches run in FP32");
   RS_CHECK_ARG(action_driven(p->controller), "env_run draws actions: discrete or waypoint controller");
-  if (p->scenario != RS_SCN_NAVIGATION) {
-    set_error("mixed-size batches run the Navigation scenario");
-    return RS_ERR_UNSUPPORTED;
-  }
   RS_CHECK_ARG(b->num_envs == plan->num_envs, "batch has %d envs, plan %d", b->num_envs,
                plan->num_envs);
   RS_CHECK_ARG(b->x && b->y && b->theta && b->goal_x && b->goal_y && b->step && b->episode,
@@ -355,10 +359,7 @@ rs_status rs_autotune(rs_ctx *ctx, const rs_params *p, const int32_t *robots, in
   if (s != RS_OK) return s;
   RS_CHECK_ARG(p->dtype == RS_F32 && action_driven(p->controller),
                "autotune runs the FP32 path of an action-driven controller");
-  if (p->scenario != RS_SCN_NAVIGATION) {
-    set_error("autotune runs the Navigation scenario");
-    return RS_ERR_UNSUPPORTED;
-  }
+
   for (int32_t k = 0; k < count; ++k)
     RS_CHECK_ARG(robots[k] >= 2 && robots[k] <= RS_MAX_ROBOTS, "robots[%d] = %d outside 2..16",
                  k, robots[k]);

@@ -308,10 +308,7 @@ rs_status rs_server_create(rs_ctx *ctx, const rs_params *p, int64_t hbm_budget_b
   if (st != RS_OK) return st;
   RS_CHECK_ARG(p->dtype == RS_F32 && action_driven(p->controller),
                "the server runs the FP32 path of an action-driven controller");
-  if (p->scenario != RS_SCN_NAVIGATION) {
-    set_error("the server runs the Navigation scenario");
-    return RS_ERR_UNSUPPORTED;
-  }
+
   RS_CHECK_ARG(hbm_budget_bytes >= 4096, "budget too small");
   RS_CHECK_ARG(tick_steps >= 1, "tick_steps must be >= 1");
   *out = nullptr;

@@ -1,6 +1,7 @@
-"""GPU parity of the Predator-Prey scenario (env_reset, env_step, rollout)
-against the FP64 oracle, teacher-forced: every step starts both sides from the
-GPU's state.
+"""GPU parity of the Predator-Prey scenario (env_reset, env_step, the
+mixed-size env_reset_mixed / env_run and, in test_gpu_rollout, the fused
+rollout) against the FP64 oracle, teacher-forced: every step starts both sides
+from the GPU's state.
 
 Tolerances as in the Navigation tests (FP32: positions 1e-5 m, heading
 6.6e-5 rad, observations 1e-5; FP64: 1e-9). Decisions taken in floating
@@ -157,11 +158,61 @@ def test_pp_prey_flees_on_the_gpu(orc):
     np.testing.assert_allclose(host(b.goal_y), 0.0, rtol=0, atol=1e-15)
 
 
-def test_pp_is_rejected_where_unsupported():
+def test_pp_mixed_batch_env_run(orc):
+    """Mixed-size batch: env_reset_mixed puts the prey at the first goal draw
+    of every env; then one env_run step at a time is compared with the oracle
+    (teacher-forced, bands as above)."""
+    import torch
+
     R, ctx = ctx_and_lib()
-    p = R.params(scenario=R.RS_SCN_PREDATOR_PREY)
-    plan = R.Plan(ctx, np.array([3, 4], np.int32))
-    b = R.Batch.empty(2, 0, total_robots=plan.total_robots)
+    counts = synth.uneven_sizes(7, 120)
+    E = len(counts)
+    off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    kw = dict(scenario=1, controller=2, max_steps=100, seed=8)
+    p = R.params(**kw)
+    po = orc.Params(**kw)
+    plan = R.Plan(ctx, counts, None)
+    b = R.Batch.empty(E, 0, total_robots=plan.total_robots)
     b.robots = 0
-    with pytest.raises(R.RobostepError):
-        R.env_run(ctx, p, plan, b, 1)
+    banner("pp mixed env_run")
+    R.env_reset_mixed(ctx, p, plan, b)
+    torch.cuda.synchronize()
+    gx0 = host(b.goal_x)
+    for e, n in enumerate(counts):
+        ogx = orc.reset_env(po, e, 0, int(n))[3]
+        np.testing.assert_array_equal(gx0[off[e]:off[e + 1]], ogx.astype(np.float32))
+    b.step.copy_(torch.from_numpy(np.random.default_rng(3).integers(90, 100, E).astype(np.int32)).cuda())
+    rew = torch.zeros(E, device="cuda")
+    done = torch.zeros(E, dtype=torch.uint8, device="cuda")
+    stats = {"tags": 0, "resets": 0, "band": 0}
+    for t in range(12):
+        before = {k: host(getattr(b, a)).astype(np.float64) for k, a in
+                  (("x", "x"), ("y", "y"), ("th", "theta"), ("gx", "goal_x"), ("gy", "goal_y"))}
+        st0, ep0 = host(b.step).copy(), host(b.episode).copy()
+        R.env_run(ctx, p, plan, b, 1, t_global0=40 + t, reward_out=rew, done_out=done)
+        torch.cuda.synchronize()
+        ax, ay, ath, agx = host(b.x), host(b.y), host(b.theta), host(b.goal_x)
+        grw, gdn = host(rew), host(done)
+        for e, n in enumerate(counts):
+            n = int(n)
+            sl = slice(off[e], off[e + 1])
+            one = {k: v[sl].copy() for k, v in before.items()}
+            one["step"], one["episode"] = int(st0[e]), int(ep0[e])
+            out = orc.env_step(po, one, e, 40 + t)
+            assert out["status"] != 2
+            assert out["done"] == gdn[e]
+            stats["resets"] += out["done"]
+            assert np.abs(one["x"] - ax[sl]).max() <= 1e-5
+            assert np.abs(one["y"] - ay[sl]).max() <= 1e-5
+            assert angle_diff(one["th"], ath[sl]).max() <= 6.6e-5
+            if abs(one["gx"][0] - agx[off[e]]) > 1e-5:
+                assert prey_band(orc, po, before["x"][sl], before["y"][sl], before["gx"][sl][0],
+                                 before["gy"][sl][0], agx[off[e]], host(b.goal_y)[off[e]])
+                stats["band"] += 1
+                continue
+            if out["reward"] != grw[e]:
+                assert tag_band(po, one["x"], one["y"], one["gx"][0], one["gy"][0])
+                stats["band"] += 1
+            stats["tags"] += int(out["reward"] > 0)
+    print(stats)
+    assert stats["resets"] >= E // 2 and stats["tags"] > 0 and stats["band"] <= 3
