@@ -133,8 +133,11 @@ template <int G> __device__ __forceinline__ bool group_any(bool pred, int lane) 
 // (lane ^ 2), quad_perm [1,2,3,0] = 0x39, [3,0,1,2] = 0x93, row_ror:n =
 // 0x120 + n (lane l reads lane (l - n) mod 16 of its row), row_mirror = 0x140
 // (l reads 15 - l), row_half_mirror = 0x141 (l reads 7 - l within its half).
+// Every control used here reads a lane of the caller's own row (and group),
+// so no source is out of bounds: with bound_ctrl the move carries no old
+// value to initialise.
 template <int CTRL> __device__ __forceinline__ int dpp_i32(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
 }
 template <int CTRL> __device__ __forceinline__ float dpp(float v) {
   return __int_as_float(dpp_i32<CTRL>(__float_as_int(v)));
