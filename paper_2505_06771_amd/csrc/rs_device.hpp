@@ -192,6 +192,15 @@ template <int G, typename T> __device__ __forceinline__ T gmin(T v) {
   return gred<G>(v, [](T a, T b) { return a < b ? a : b; });
 }
 
+// LDS writes of the wavefront's lanes visible to its other lanes (and kept
+// ahead of the reads that follow): wavefront-scope fences around a wave
+// barrier, no hardware wait.
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Compile-time loop: f(std::integral_constant<int, K>) for K in [B, E).
 template <int B, int E, typename F> __device__ __forceinline__ void static_for(F &&f) {
   if constexpr (B < E) {

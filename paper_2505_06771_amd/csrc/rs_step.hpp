@@ -132,30 +132,82 @@ __device__ void reset_env(ConstRef<T> K, uint32_t env_id, uint32_t episode, int 
 // pulled in by r_s/2; the prey takes the candidate with the largest squared
 // distance to the closest robot centre (x, y of the calling lanes, before
 // they move), the first on ties. (qx, qy) is group-uniform in and out.
+// Every lane forms all 17 candidates (group-uniform) and its robot's distance
+// to each. With G >= 4 the distances go through the group's QP scratch in LDS
+// (unused at this point of the step): lane i then takes the minimum over the
+// robots for candidates i, i + G, ..., and one arg-max butterfly picks the
+// winner; with G = 2 a group minimum per candidate is as cheap.
 template <typename T, int G, typename CS>
-__device__ __forceinline__ void prey_move(const CS &C, bool on, T x, T y, T &qx, T &qy) {
+__device__ __forceinline__ void prey_move(const CS &C, QPScratch<T, G> *sh, int lane, int i,
+                                          bool on, T x, T y, T &qx, T &qy) {
+  constexpr int NCAND = 17;
   constexpr double kC = 0.92387953251128674, kH = 0.70710678118654752, kS = 0.38268343236508977;
   constexpr double dir_c[16] = {1, kC, kH, kS, 0, -kS, -kH, -kC, -1, -kC, -kH, -kS, 0, kS, kH, kC};
   constexpr double dir_s[16] = {0, kS, kH, kC, 1, kC, kH, kS, 0, -kS, -kH, -kC, -1, -kC, -kH, -kS};
   const T far = T(1e30);
   const T st = C.prey_step;
-  T dx = qx - x, dy = qy - y;
-  T best = gmin<G>(on ? dx * dx + dy * dy : far);
-  T bx = qx, by = qy;
-  static_for<0, 16>([&](auto kc) {
+  T cx[NCAND], cy[NCAND];
+  cx[0] = qx;
+  cy[0] = qy;
+  static_for<1, NCAND>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
-    const T cx = tclamp(qx + st * T(dir_c[k]), C.xwl, C.xwh);
-    const T cy = tclamp(qy + st * T(dir_s[k]), C.ywl, C.ywh);
-    const T ex = cx - x, ey = cy - y;
-    const T sc = gmin<G>(on ? ex * ex + ey * ey : far);
-    if (sc > best) {
-      best = sc;
-      bx = cx;
-      by = cy;
-    }
+    cx[k] = tclamp(qx + st * T(dir_c[k - 1]), C.xwl, C.xwh);
+    cy[k] = tclamp(qy + st * T(dir_s[k - 1]), C.ywl, C.ywh);
   });
-  qx = bx;
-  qy = by;
+  if constexpr (G == 2 || sizeof(QPScratch<T, G>) < sizeof(T) * NCAND * G) {
+    T best = T(-1), bx = qx, by = qy;
+    static_for<0, NCAND>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      const T ex = cx[k] - x, ey = cy[k] - y;
+      const T sc = gmin<G>(on ? ex * ex + ey * ey : far);
+      const bool bt = sc > best;
+      best = bt ? sc : best;
+      bx = bt ? cx[k] : bx;
+      by = bt ? cy[k] : by;
+    });
+    qx = bx;
+    qy = by;
+  } else {
+    T *d = reinterpret_cast<T *>(sh);  // [candidate][robot]
+    static_for<0, NCAND>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      const T ex = cx[k] - x, ey = cy[k] - y;
+      d[k * G + i] = on ? ex * ex + ey * ey : far;
+    });
+    wave_lds_fence();
+    T best = T(-1);
+    int bk = NCAND;
+    for (int k = i; k < NCAND; k += G) {  // ascending: the first maximum stays
+      T m = d[k * G];
+#pragma unroll
+      for (int j = 1; j < G; ++j) m = tmin(m, d[k * G + j]);
+      const bool bt = m > best;
+      best = bt ? m : best;
+      bk = bt ? k : bk;
+    }
+    wave_lds_fence();  // the scratch is the QP's again
+    // arg-max over the group, ties to the lower candidate index
+    auto merge = [&](auto c) {
+      constexpr int CT = decltype(c)::value;
+      const T w = dpp<CT>(best);
+      const int wk = dpp<CT>(bk);
+      const bool bt = (w > best) | ((w == best) & (wk < bk));
+      best = bt ? w : best;
+      bk = bt ? wk : bk;
+    };
+    merge(std::integral_constant<int, 0xB1>{});
+    if constexpr (G >= 4) merge(std::integral_constant<int, 0x4E>{});
+    if constexpr (G >= 8) merge(std::integral_constant<int, 0x141>{});
+    if constexpr (G >= 16) merge(std::integral_constant<int, 0x140>{});
+    T bx = qx, by = qy;
+    static_for<1, NCAND>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      bx = bk == k ? cx[k] : bx;
+      by = bk == k ? cy[k] : by;
+    });
+    qx = bx;
+    qy = by;
+  }
 }
 
 // Observation of robot i: x, y, cos th, sin th, (x_j - x_i, y_j - y_i) for
@@ -273,7 +325,7 @@ __device__ StepOut<T> env_step_group(ConstRef<T> K, int qp_cap, QPScratch<T, G> 
     const int base = lane & ~(G - 1);
     qx = __shfl(gx, base, 64);
     qy = __shfl(gy, base, 64);
-    prey_move<T, G>(*K.get(), on, x, y, qx, qy);
+    prey_move<T, G>(*K.get(), sh, lane, i, on, x, y, qx, qy);
   }
   T lox, hix, loy, hiy;
   wall_bounds(*K.get(), px, py, lox, hix, loy, hiy);
