@@ -146,24 +146,29 @@ __device__ __forceinline__ void prey_move(const CS &C, QPScratch<T, G> *sh, int 
   constexpr double dir_s[16] = {0, kS, kH, kC, 1, kC, kH, kS, 0, -kS, -kH, -kC, -1, -kC, -kH, -kS};
   const T far = T(1e30);
   const T st = C.prey_step;
-  T cx[NCAND], cy[NCAND];
-  cx[0] = qx;
-  cy[0] = qy;
-  static_for<1, NCAND>([&](auto kc) {
+  // candidate k's position (the same arithmetic wherever it is formed)
+  auto cand = [&](auto kc, T &cx, T &cy) {
     constexpr int k = decltype(kc)::value;
-    cx[k] = tclamp(qx + st * T(dir_c[k - 1]), C.xwl, C.xwh);
-    cy[k] = tclamp(qy + st * T(dir_s[k - 1]), C.ywl, C.ywh);
-  });
+    if constexpr (k == 0) {
+      cx = qx;
+      cy = qy;
+    } else {
+      cx = tclamp(qx + st * T(dir_c[k - 1]), C.xwl, C.xwh);
+      cy = tclamp(qy + st * T(dir_s[k - 1]), C.ywl, C.ywh);
+    }
+  };
   if constexpr (G == 2 || sizeof(QPScratch<T, G>) < sizeof(T) * NCAND * G) {
     T best = T(-1), bx = qx, by = qy;
     static_for<0, NCAND>([&](auto kc) {
       constexpr int k = decltype(kc)::value;
-      const T ex = cx[k] - x, ey = cy[k] - y;
+      T cx, cy;
+      cand(kc, cx, cy);
+      const T ex = cx - x, ey = cy - y;
       const T sc = gmin<G>(on ? ex * ex + ey * ey : far);
       const bool bt = sc > best;
       best = bt ? sc : best;
-      bx = bt ? cx[k] : bx;
-      by = bt ? cy[k] : by;
+      bx = bt ? cx : bx;
+      by = bt ? cy : by;
     });
     qx = bx;
     qy = by;
@@ -171,7 +176,9 @@ __device__ __forceinline__ void prey_move(const CS &C, QPScratch<T, G> *sh, int 
     T *d = reinterpret_cast<T *>(sh);  // [candidate][robot]
     static_for<0, NCAND>([&](auto kc) {
       constexpr int k = decltype(kc)::value;
-      const T ex = cx[k] - x, ey = cy[k] - y;
+      T cx, cy;
+      cand(kc, cx, cy);
+      const T ex = cx - x, ey = cy - y;
       d[k * G + i] = on ? ex * ex + ey * ey : far;
     });
     wave_lds_fence();
@@ -199,14 +206,17 @@ __device__ __forceinline__ void prey_move(const CS &C, QPScratch<T, G> *sh, int 
     if constexpr (G >= 4) merge(std::integral_constant<int, 0x4E>{});
     if constexpr (G >= 8) merge(std::integral_constant<int, 0x141>{});
     if constexpr (G >= 16) merge(std::integral_constant<int, 0x140>{});
-    T bx = qx, by = qy;
+    // the winner's direction, then its position formed as above
+    T dc = T(0), ds = T(0);
     static_for<1, NCAND>([&](auto kc) {
       constexpr int k = decltype(kc)::value;
-      bx = bk == k ? cx[k] : bx;
-      by = bk == k ? cy[k] : by;
+      dc = bk == k ? T(dir_c[k - 1]) : dc;
+      ds = bk == k ? T(dir_s[k - 1]) : ds;
     });
-    qx = bx;
-    qy = by;
+    if (bk > 0) {
+      qx = tclamp(qx + st * dc, C.xwl, C.xwh);
+      qy = tclamp(qy + st * ds, C.ywl, C.ywh);
+    }
   }
 }
 
