@@ -521,7 +521,6 @@ __device__ __noinline__ QPLoopOut<T> qp_active_set(QPScratch<T, G> *sh, int lane
   // --- geometry of the owned pairs ------------------------------------------
   T cdx[KH], cdy[KH], cb[KH], crn[KH];
   int cpid[KH];
-  bool coincide = false;
   static_for<1, KH + 1>([&](auto kc) {
     constexpr int K = decltype(kc)::value;
     const T pxj = grot<G, K>(px, lane), pyj = grot<G, K>(py, lane);
@@ -539,7 +538,6 @@ __device__ __noinline__ QPLoopOut<T> qp_active_set(QPScratch<T, G> *sh, int lane
     cb[K - 1] = bb;
     crn[K - 1] = d2 > T(0) ? T(0.35355339059327373) * rsqrt_t(d2) : T(0);
     cpid[K - 1] = (cand && d2 > T(0)) ? ((ia ? i : j) << 4 | (ia ? j : i)) : -1;
-    if (cand && !(d2 > T(0)) && bb < T(0)) coincide = true;
   });
   // --- start: clip to the box; active bounds fix their coordinate ----------
   int fx = 0, fy = 0;

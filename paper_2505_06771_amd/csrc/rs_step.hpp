@@ -138,7 +138,7 @@ __device__ void reset_env(ConstRef<T> K, uint32_t env_id, uint32_t episode, int 
 // robots for candidates i, i + G, ..., and one arg-max butterfly picks the
 // winner; with G = 2 a group minimum per candidate is as cheap.
 template <typename T, int G, typename CS>
-__device__ __forceinline__ void prey_move(const CS &C, QPScratch<T, G> *sh, int lane, int i,
+__device__ __forceinline__ void prey_move(const CS &C, QPScratch<T, G> *sh, int i,
                                           bool on, T x, T y, T &qx, T &qy) {
   constexpr int NCAND = 17;
   constexpr double kC = 0.92387953251128674, kH = 0.70710678118654752, kS = 0.38268343236508977;
@@ -335,7 +335,7 @@ __device__ StepOut<T> env_step_group(ConstRef<T> K, int qp_cap, QPScratch<T, G> 
     const int base = lane & ~(G - 1);
     qx = __shfl(gx, base, 64);
     qy = __shfl(gy, base, 64);
-    prey_move<T, G>(*K.get(), sh, lane, i, on, x, y, qx, qy);
+    prey_move<T, G>(*K.get(), sh, i, on, x, y, qx, qy);
   }
   T lox, hix, loy, hiy;
   wall_bounds(*K.get(), px, py, lox, hix, loy, hiy);
