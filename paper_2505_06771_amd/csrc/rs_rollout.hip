@@ -367,9 +367,11 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
 }
 
 // Kernel for N robots: a compile-time robot count for N = 8 (8 lanes, no
-// idle lane), the lane-group width with a run-time count otherwise.
+// idle lane) and N = 3 (the team size of the paper's scenarios), the
+// lane-group width with a run-time count otherwise.
 template <bool PP> static const void *rollout_kernel_for(int N) {
   if (N == 8) return reinterpret_cast<const void *>(&k_rollout<8, 8, PP>);
+  if (N == 3) return reinterpret_cast<const void *>(&k_rollout<4, 3, PP>);  // the paper's teams
   switch (pow2_group(N)) {
     case 2: return reinterpret_cast<const void *>(&k_rollout<2, 0, PP>);
     case 4: return reinterpret_cast<const void *>(&k_rollout<4, 0, PP>);
