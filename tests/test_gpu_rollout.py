@@ -51,10 +51,11 @@ def run_and_check(orc, n, E, H, seed, sample_envs=None, sample_steps=None, step0
 
     R, ctx = ctx_and_lib()
     dim = 2 * n + 4
+    extra = extra or {}
     st = synth.random_states(seed, E, n) if E <= 4096 else None
     if st is None:
         b = R.Batch.empty(E, n, env_id_base=0)
-        R.env_reset(ctx, R.params(seed=seed), b)
+        R.env_reset(ctx, R.params(seed=seed, **extra), b)
     else:
         b = batch_from_states(R, st, n, torch.float32, env_id_base=0,
                               step=step0 if step0 is not None else None)
@@ -66,7 +67,6 @@ def run_and_check(orc, n, E, H, seed, sample_envs=None, sample_steps=None, step0
     done = torch.zeros(H * E, dtype=torch.uint8, device="cuda")
     step_init = host(b.step).astype(np.int32).copy()
     ep_init = host(b.episode).astype(np.int32).copy()
-    extra = extra or {}
     p = R.params(seed=seed, **extra)
     po = orc.Params(seed=seed, **extra)
     t0 = 1000
@@ -193,6 +193,20 @@ def test_rollout_full_size_sampled(orc):
     envs = np.sort(rng.choice(E, 24, replace=False))
     envs = np.concatenate([envs, [0, E - 1]])
     run_and_check(orc, n, E, H, seed=0, sample_envs=envs, sample_steps=[0, 1, 63, 126, 127])
+
+
+def test_rollout_predator_prey_full_size_sampled(orc):
+    """The Predator-Prey shape of the benchmark suite: 43690 envs x 3 robots
+    (the paper's team size), 128 steps with 100-step episodes from a fresh
+    reset, so every env ends exactly one episode inside the launch; sampled
+    envs and steps around that end."""
+    E, n, H = 43690, 3, 128
+    rng = np.random.default_rng(1)
+    envs = np.concatenate([np.sort(rng.choice(E, 24, replace=False)), [0, E - 1]])
+    _, _, _, _, dn = run_and_check(orc, n, E, H, seed=3, sample_envs=envs,
+                                   sample_steps=[0, 1, 63, 98, 99, 100, 127],
+                                   extra=dict(scenario=1, controller=2, max_steps=100))
+    assert (dn.sum(axis=0) == 1).all()
 
 
 def test_rollout_graph_replay_is_deterministic(orc):
