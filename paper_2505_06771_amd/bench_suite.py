@@ -189,11 +189,16 @@ def uneven_8192(R, ctx, seed=0, steps=1000, autotune=True):
     return out
 
 
-def serving(R, ctx, seed=0, count=600, skip=60, budget=16 << 30, tick=32, rate=None,
-            plain_count=120):
+def serving(R, ctx, seed=0, count=2000, skip=200, budget=64 << 30, stress_budget=2 << 20,
+            tick=32, rate=None, plain_count=120):
     """Continuous batching vs plain per-request launches on the same Poisson
     arrival process. `rate` defaults to 0.7 x the saturated capacity of the
-    served path (measured first on a burst) / mean request work."""
+    served path (measured first on a burst) / mean request work. The served
+    path runs twice: at the nominal HBM budget and at `stress_budget`, small
+    enough that admission queues requests (2 MiB holds one request of the
+    largest size, 4096 envs x 16 robots, 1.45 MB). The plain path serves only
+    the first `plain_count` requests: each runs alone with one launch per
+    step, about a third of a second each."""
     import torch
 
     from paper_2505_06771_amd import synth
@@ -217,7 +222,7 @@ def serving(R, ctx, seed=0, count=600, skip=60, budget=16 << 30, tick=32, rate=N
         rate = 0.7 * cap / mean_work
     reqs = synth.request_stream(seed, count, rate)
 
-    def run_served():
+    def run_served(budget):
         srv = R.Server(ctx, p, budget, tick)
         lat, late = {}, {}
         start = time.perf_counter()
@@ -242,7 +247,7 @@ def serving(R, ctx, seed=0, count=600, skip=60, budget=16 << 30, tick=32, rate=N
         wall = time.perf_counter() - start
         st = srv.stats()
         srv.close()
-        return lat, wall, st.robot_steps
+        return lat, wall, st.robot_steps, st.peak_bytes
 
     def run_plain(n_req):
         """FIFO, one request at a time, reset + one env_step launch per step."""
@@ -262,8 +267,10 @@ def serving(R, ctx, seed=0, count=600, skip=60, budget=16 << 30, tick=32, rate=N
             work += r["envs"] * r["robots"] * r["horizon"]
         return lat, time.perf_counter() - start, work
 
-    lat_s, wall_s, work_s = run_served()
+    lat_s, wall_s, work_s, _ = run_served(budget)
     ls = np.array([lat_s[i] for i in range(skip, count)])
+    lat_q, wall_q, work_q, peak_q = run_served(stress_budget)
+    lq = np.array([lat_q[i] for i in range(skip, count)])
     n_plain = min(plain_count, count)
     lat_p, wall_p, work_p = run_plain(n_plain)
     lp = np.array([lat_p[i] for i in range(min(skip, n_plain // 2), n_plain)])
@@ -273,6 +280,10 @@ def serving(R, ctx, seed=0, count=600, skip=60, budget=16 << 30, tick=32, rate=N
             "served_p50_ms": float(np.percentile(ls, 50) * 1e3),
             "served_p99_ms": float(np.percentile(ls, 99) * 1e3),
             "served_robot_steps_per_s": work_s / wall_s,
+            "stress_budget_bytes": stress_budget, "stress_peak_bytes": peak_q,
+            "stress_p50_ms": float(np.percentile(lq, 50) * 1e3),
+            "stress_p99_ms": float(np.percentile(lq, 99) * 1e3),
+            "stress_robot_steps_per_s": work_q / wall_q,
             "plain_requests": n_plain,
             "plain_p50_ms": float(np.percentile(lp, 50) * 1e3),
             "plain_p99_ms": float(np.percentile(lp, 99) * 1e3),
