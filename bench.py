@@ -171,12 +171,13 @@ def main():
     ap.add_argument("--suite", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
-    ap.add_argument("--suite-out", default=os.path.join(ROOT, "gpurun_out", "bench_suite.json"))
+    ap.add_argument("--suite-out", default=os.path.join(ROOT, "results", "bench_suite.json"))
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus} GPUs, world size {world}); "
-              "environments shard independently across GPUs, see the design notes", file=sys.stderr)
+              "environments are independent, so N GPUs would each run this one-GPU workload "
+              "on their own share of the envs", file=sys.stderr)
         sys.exit(2)
     import torch
 

@@ -13,7 +13,7 @@
  * Everything is FP64 and written for clarity, not speed: dense matrices, no
  * blocking, no pruning. The paper gives no equations for the simulator, so the
  * constants and the readings of unspecified details are documented on each
- * function (and collected in the design notes of the repository).
+ * function.
  */
 #ifndef ROBOSTEP_ORACLE_H
 #define ROBOSTEP_ORACLE_H

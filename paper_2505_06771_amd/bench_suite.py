@@ -392,7 +392,7 @@ if __name__ == "__main__":
     import argparse
 
     ap = argparse.ArgumentParser()
-    ap.add_argument("--out", default="gpurun_out/bench_suite.json")
+    ap.add_argument("--out", default="results/bench_suite.json")
     ap.add_argument("--only", nargs="*")
     a = ap.parse_args()
     run_all(a.out, which=tuple(a.only) if a.only else
