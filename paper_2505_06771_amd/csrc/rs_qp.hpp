@@ -515,6 +515,9 @@ __device__ __noinline__ QPLoopOut<T> qp_active_set(QPScratch<T, G> *sh, int lane
   C.eps_z = eps_z;
   C.eps_r = eps_r;
   C.qp_cap = qp_cap;
+  // the wavefronts in this loop are the slowest of a launch: give them the
+  // first claim on issue slots over the other wavefront of their SIMD
+  __builtin_amdgcn_s_setprio(1);
   QPInfo info{0, 0, 0, 0};
   bool dead = false;
   T ux, uy;
@@ -861,6 +864,7 @@ __device__ __noinline__ QPLoopOut<T> qp_active_set(QPScratch<T, G> *sh, int lane
     out.sb[a] = sb[a];
     out.slam[a] = slam[a];
   }
+  __builtin_amdgcn_s_setprio(0);
   return out;
 }
 
