@@ -133,3 +133,59 @@ def test_noise_enters_ahead_of_preclip_and_certificate(orc, controller):
         assert ref["y"][i] == pytest.approx(st["y"][i] + p.dt * v * s, abs=1e-15)
         assert ref["th"][i] == pytest.approx(st["th"][i] + p.dt * w, abs=1e-14) or \
             abs(abs(ref["th"][i] - st["th"][i] - p.dt * w) - 2 * math.pi) < 1e-12
+
+
+# ---- go-to-goal controller (single-integrator controller of Sec. 4.1,
+# proportional law on the projection point) ---------------------------------
+
+@pytest.mark.parametrize("kp", [1.0, 2.5])
+def test_goto_goal_command_at_special_headings(orc, kp):
+    """u_nom = kp (g - p) with p the projection point, not the centre: at
+    heading 0 the point sits l ahead in x, at heading pi/2 l ahead in y."""
+    p = orc.Params(controller=1, kp=kp)
+    l = p.proj_dist
+    x0, y0, gx, gy = 0.3, -0.2, 0.37, -0.11
+    st = _state([x0, -1.0], [y0, 0.5], [0.0, math.pi / 2], [gx, -0.9], [gy, 0.62])
+    unx, uny, _ = orc.nominal_command(p, st, 0, 0)
+    assert unx[0] == pytest.approx(kp * (gx - (x0 + l)), abs=1e-15)
+    assert uny[0] == pytest.approx(kp * (gy - y0), abs=1e-15)
+    # heading pi/2: the projection point is (x, y + l)
+    assert unx[1] == pytest.approx(kp * (-0.9 - (-1.0)), abs=1e-14)
+    assert uny[1] == pytest.approx(kp * (0.62 - (0.5 + l)), abs=1e-14)
+    # using the centre instead would differ by kp * l in the heading direction
+    assert abs(unx[0] - kp * (gx - x0)) > 0.5 * kp * l
+    assert abs(uny[1] - kp * (0.62 - 0.5)) > 0.5 * kp * l
+
+
+def test_goto_goal_command_is_zero_at_the_goal(orc):
+    p = orc.Params(controller=1)
+    th = np.array([0.3, -2.0, 2.9])
+    x, y = np.array([0.1, -0.5, 0.8]), np.array([0.2, 0.4, -0.3])
+    gx = x + p.proj_dist * np.cos(th)  # the goal is the projection point itself
+    gy = y + p.proj_dist * np.sin(th)
+    unx, uny, _ = orc.nominal_command(p, _state(x, y, th, gx, gy), 0, 0)
+    assert (unx == 0.0).all() and (uny == 0.0).all()
+
+
+def test_goto_goal_large_error_is_preclipped_to_vmax(orc):
+    """A far goal gives |kp (g - p)| > v_max: the executed command is the
+    pre-clipped one, v_max along g - p (no barrier row or wall binds for two
+    robots far apart in the middle of the arena). Without wheel saturation the
+    unicycle step shows it: v = u.(c, s), w = u.(-s, c) / l."""
+    p = orc.Params(controller=1, wheel_radius=0.0, max_steps=0, goal_radius=0.0)
+    l, dt, vmax = p.proj_dist, p.dt, p.v_max
+    st = _state([-0.6, 0.6], [0.0, 0.0], [0.0, math.pi / 2], [0.9, 0.2], [0.7, -0.8])
+    start = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in st.items()}
+    out = orc.env_step(p, st, 0, 0)
+    assert out["status"] == 0 and out["infeasible"] == 0
+    for i in range(2):
+        th = start["th"][i]
+        c, s = math.cos(th), math.sin(th)
+        px, py = start["x"][i] + l * c, start["y"][i] + l * s
+        ex, ey = start["gx"][i] - px, start["gy"][i] - py
+        assert math.hypot(ex, ey) > 2 * vmax       # far outside the clip radius
+        ux, uy = vmax * ex / math.hypot(ex, ey), vmax * ey / math.hypot(ex, ey)
+        v, w = ux * c + uy * s, (-s * ux + c * uy) / l
+        assert st["x"][i] == pytest.approx(start["x"][i] + dt * v * c, abs=1e-15)
+        assert st["y"][i] == pytest.approx(start["y"][i] + dt * v * s, abs=1e-15)
+        assert st["th"][i] == pytest.approx(th + dt * w, abs=1e-14)

@@ -171,3 +171,54 @@ def test_wall_bounds_closed_form(orc):
     assert hi_y[1] == pytest.approx(min(0.2, kb * (1.0 - 0.085 - 0.80) ** 3), rel=1e-14)
     assert lo_y[2] == pytest.approx(-kb * (-0.86 + 1.0 - 0.085) ** 3, rel=1e-14)
     assert hi_x[2] == 0.2 and lo_x[2] == -0.2
+
+
+# ---- the violation metric (largest normalised row excess) -----------------
+
+def _wall_hi(p, c, wall):
+    """Upper bound of one coordinate from its closed form: the speed limit or
+    the cubic wall certificate of the wall pulled in by r_s / 2."""
+    m = wall - p.safety_radius / 2 - c
+    return min(p.v_max, p.boundary_gain_factor * p.barrier_gain * m ** 3)
+
+
+def test_max_violation_of_a_pair_row_is_normalised_by_its_norm(orc):
+    """Pair row -2 D.u_i + 2 D.u_j <= gamma h^3 has norm 2 sqrt(2) |D|; the
+    metric is the row excess divided by it (m/s)."""
+    p = orc.Params()
+    px, py = np.array([0.0, 0.2]), np.array([0.0, 0.0])
+    dx, dy = px[0] - px[1], py[0] - py[1]
+    b = p.barrier_gain * (dx * dx + dy * dy - p.safety_radius ** 2) ** 3
+    ux, uy = np.array([0.1, -0.1]), np.array([0.0, 0.0])  # head-on, inside the box
+    excess = (-2 * dx * ux[0] - 2 * dy * uy[0]) + (2 * dx * ux[1] + 2 * dy * uy[1]) - b
+    assert excess > 0.05
+    want = excess / (2 * math.sqrt(2) * math.hypot(dx, dy))
+    got = orc.max_violation(p, px, py, ux, uy)
+    assert got == pytest.approx(want, rel=1e-14)
+    assert abs(got - excess) > 0.01  # an unnormalised excess would fail
+    # moving apart satisfies the row: nothing is violated
+    assert orc.max_violation(p, px, py, -ux, uy) == 0.0
+
+
+def test_max_violation_of_bounds_and_the_max_over_rows(orc):
+    p = orc.Params()
+    # robot 0 near the right wall: its x bound is the wall certificate
+    px, py = np.array([1.5, -1.0]), np.array([0.0, 0.5])
+    hi0 = _wall_hi(p, px[0], p.x_max)
+    assert hi0 < 1e-3
+    ux, uy = np.array([0.05, 0.0]), np.array([0.0, 0.0])
+    assert orc.max_violation(p, px, py, ux, uy) == pytest.approx(0.05 - hi0, rel=1e-14)
+    # a speed-box excess of robot 1 in y (lower bound -v_max)
+    uy2 = np.array([0.0, -0.32])
+    assert orc.max_violation(p, px, py, np.zeros(2), uy2) == pytest.approx(0.12, rel=1e-14)
+    # both at once: the metric is the larger of the two
+    got = orc.max_violation(p, px, py, ux, uy2)
+    assert got == pytest.approx(max(0.05 - hi0, 0.12), rel=1e-14)
+    # three robots: a violated pair row next to a smaller bound excess
+    px3, py3 = np.array([0.0, 0.19, -1.0]), np.array([0.0, 0.0, 0.5])
+    ux3, uy3 = np.array([0.2, -0.2, 0.0]), np.array([0.0, 0.0, 0.21])
+    dx = px3[0] - px3[1]
+    b = p.barrier_gain * (dx * dx - p.safety_radius ** 2) ** 3
+    pair = (-2 * dx * ux3[0] + 2 * dx * ux3[1] - b) / (2 * math.sqrt(2) * abs(dx))
+    assert pair > 0.01
+    assert orc.max_violation(p, px3, py3, ux3, uy3) == pytest.approx(max(pair, 0.01), rel=1e-13)
