@@ -28,6 +28,10 @@
  *  - Per-environment infeasibility of the QP is data, not an error: the
  *    `infeasible` flag is set and the command falls back to the per-coordinate
  *    clip of the nominal command to its bounds (midpoint where they cross).
+ *  - A certificate QP that stops at its iteration cap (qp_max_iters) or on a
+ *    numerical failure is never silent: the per-env status outputs carry 2,
+ *    the optional qp_stats counters count it, and every call adds it to the
+ *    context's failure counters (rs_qp_failures).
  */
 #ifndef ROBOSTEP_H
 #define ROBOSTEP_H
@@ -118,6 +122,30 @@ typedef struct {
 typedef struct rs_ctx rs_ctx;
 typedef struct rs_plan rs_plan;
 
+/* Per-env certificate statistics (the optional `qp_stats` outputs): int32
+ * [E][RS_QPS_COUNT], accumulated (+=) over every solve of the call, so a
+ * caller zeroes them first. Each solve adds 1 to exactly one of slots 0..7:
+ * the stage that produced the command (BOX: no row violated at the box clip
+ * of the nominal command; ONE_ROW: one violated row, projected in closed
+ * form; TWO_ROWS: two violated rows on four distinct robots; SHARED_ROBOT:
+ * two violated rows through one robot, 2 x 2 Gram system; ACTIVE_SET: the
+ * register-resident dual active-set loop; GENERAL: the general active-set
+ * solver with its rows in LDS), or INFEASIBLE (no feasible command) or
+ * CAPPED (stopped by the iteration cap or a numerical failure). ITERATIONS
+ * sums the active-set iterations of the solves that ran the loop. */
+enum {
+  RS_QPS_BOX = 0,
+  RS_QPS_ONE_ROW = 1,
+  RS_QPS_TWO_ROWS = 2,
+  RS_QPS_SHARED_ROBOT = 3,
+  RS_QPS_ACTIVE_SET = 4,
+  RS_QPS_GENERAL = 5,
+  RS_QPS_INFEASIBLE = 6,
+  RS_QPS_CAPPED = 7,
+  RS_QPS_ITERATIONS = 8,
+  RS_QPS_COUNT = 9
+};
+
 void rs_params_default(rs_params *p);
 /* Validates p as every call does (host only, no device work): RS_OK or
  * RS_ERR_INVALID_ARG with the reason in rs_last_error(). */
@@ -130,6 +158,14 @@ const char *rs_last_error(void);
  * cache). */
 rs_status rs_create(int device, rs_ctx **out);
 rs_status rs_destroy(rs_ctx *ctx);
+
+/* Certificate failures counted on the device by every call on ctx
+ * (env_step, barrier_certificate, rollout, env_run, server ticks) since the
+ * context was created or last reset: solves with no feasible command
+ * (*infeasible) and solves stopped by the iteration cap or a numerical
+ * failure (*capped). Waits for all work queued on the context's device.
+ * reset != 0 zeroes both counters after reading. Either pointer may be NULL. */
+rs_status rs_qp_failures(rs_ctx *ctx, int64_t *infeasible, int64_t *capped, int32_t reset);
 
 /* ---------------------------------------------------------------------------
  * env_reset -- reset sampler (start poses uniform with a minimum separation,
@@ -192,11 +228,15 @@ rs_status env_reset(rs_ctx *ctx, const rs_params *p, const rs_batch *b, const ui
  *     cos th, sin th, (x_j - x_i, y_j - y_i) for j != i ascending, g_i - (x,y).
  * actions: [E*N] uint8 in 0..4 or NULL. reward [E] (float/double), done [E],
  * max_violation [E] float (NULL ok: largest normalised row/bound violation of
- * the command), infeasible [E] (NULL ok). obs/reward/done may be NULL.
+ * the command), infeasible [E] uint8 (NULL ok): the certificate's status,
+ * 0 solved, 1 no feasible command (per-coordinate fallback), 2 stopped by the
+ * iteration cap or a numerical failure (the intermediate command is used).
+ * qp_stats [E][RS_QPS_COUNT] int32 (NULL ok): accumulated statistics.
+ * obs/reward/done may be NULL.
  * ------------------------------------------------------------------------- */
 rs_status env_step(rs_ctx *ctx, const rs_params *p, const rs_batch *b, const uint8_t *actions,
                    int64_t t_global, void *obs, void *reward, uint8_t *done, float *max_violation,
-                   uint8_t *infeasible, void *stream);
+                   uint8_t *infeasible, int32_t *qp_stats, void *stream);
 
 /* ---------------------------------------------------------------------------
  * barrier_certificate -- steps 1 (pre-clip) and 2 of env_step alone, for
@@ -204,12 +244,14 @@ rs_status env_step(rs_ctx *ctx, const rs_params *p, const rs_batch *b, const uin
  * commands (ux_nom, uy_nom) [E*N], writes the exact minimiser (ux, uy) [E*N].
  * lambda (may be NULL): [E][N(N-1)/2] multipliers of the pairwise rows (pairs
  * i<j in lexicographic order) for the objective |u - u_nom|^2; not unique
- * under degeneracy. max_violation [E] float and infeasible [E] may be NULL.
+ * under degeneracy. max_violation [E] float, infeasible [E] (status 0/1/2 as
+ * in env_step) and qp_stats [E][RS_QPS_COUNT] (accumulated) may be NULL.
  * ------------------------------------------------------------------------- */
 rs_status barrier_certificate(rs_ctx *ctx, const rs_params *p, int32_t num_envs, int32_t robots,
                               const void *px, const void *py, const void *ux_nom,
                               const void *uy_nom, void *ux, void *uy, void *lambda,
-                              float *max_violation, uint8_t *infeasible, void *stream);
+                              float *max_violation, uint8_t *infeasible, int32_t *qp_stats,
+                              void *stream);
 
 /* ---------------------------------------------------------------------------
  * rollout -- `horizon` fused policy steps in one persistent launch (FP32 state,
@@ -222,11 +264,14 @@ rs_status barrier_certificate(rs_ctx *ctx, const rs_params *p, int32_t num_envs,
  * (stream time t_global0 + t). Outputs: obs [H][E*N][2N+4] float (may be NULL),
  * actions [H][E*N] uint8, reward [H][E] float, done [H][E] uint8. The batch
  * state is left at the post-rollout state. Requires 2N+4 <= 32.
+ * qp_stats [E][RS_QPS_COUNT] int32 (NULL ok) accumulates the certificate
+ * statistics of all H steps; it selects a separately compiled kernel that
+ * counts them (the kernel without it carries none of that code).
  * The launch is captured once per (shape, pointers) in a hipGraph and replayed.
  * ------------------------------------------------------------------------- */
 rs_status rollout(rs_ctx *ctx, const rs_params *p, const rs_batch *b, const rs_policy *policy,
                   int32_t horizon, int64_t t_global0, float *obs, uint8_t *actions,
-                  float *reward, uint8_t *done, void *stream);
+                  float *reward, uint8_t *done, int32_t *qp_stats, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Snapshot / restore (checkpoint and resume) of a batch's state: pose, goal,
@@ -269,7 +314,8 @@ int64_t rs_plan_total_robots(const rs_plan *plan);
 const int32_t *rs_plan_robot_offset(const rs_plan *plan);
 
 /* env_reset for a mixed batch (FP32): b->robots is ignored; arrays use the
- * plan's robot offsets; reset definition as env_reset. */
+ * plan's robot offsets; reset definition as env_reset. The mask [E] (NULL =
+ * all) is only read; the call allocates nothing. */
 rs_status env_reset_mixed(rs_ctx *ctx, const rs_params *p, const rs_plan *plan,
                           const rs_batch *b, const uint8_t *mask, void *stream);
 
@@ -282,14 +328,15 @@ rs_status env_reset_mixed(rs_ctx *ctx, const rs_params *p, const rs_plan *plan,
  * may be NULL): reward_out/done_out [steps][E] (rows past an env's own count
  * untouched), reward_sum [E] (accumulated: += sum of the env's rewards),
  * obs_final: observation of the final state, env e's block of N_e x (2N_e+4)
- * floats starting at rs_plan_obs_offset(plan, e). Results per env do not
+ * floats starting at rs_plan_obs_offset(plan, e); qp_stats [E][RS_QPS_COUNT]
+ * int32, accumulated certificate statistics. Results per env do not
  * depend on the other envs in the batch or on the schedule (as long as the
- * iteration cap is not reached).
+ * iteration cap is not reached: see rs_qp_failures and RS_QPS_CAPPED).
  * ------------------------------------------------------------------------- */
 rs_status env_run(rs_ctx *ctx, const rs_params *p, const rs_plan *plan, const rs_batch *b,
                   int32_t steps, const int64_t *t_start, int64_t t_global0,
                   const int32_t *steps_per_env, float *reward_out, uint8_t *done_out,
-                  float *reward_sum, float *obs_final, void *stream);
+                  float *reward_sum, float *obs_final, int32_t *qp_stats, void *stream);
 /* Offset of env e's observation block in obs_final (host query). */
 int64_t rs_plan_obs_offset(const rs_plan *plan, int32_t env);
 
@@ -301,9 +348,12 @@ int64_t rs_plan_obs_offset(const rs_plan *plan, int32_t env);
  * coordinate descent from the default schedule: block size in {64, 128, 256},
  * then per size lanes per env (envs per wavefront = 64 / lanes) doubled,
  * then the active-set iteration cap in {2N+4, 4N+8}. A change is kept when
- * every final position matches the default-schedule, widest-cap reference
- * within steps * dt * tol (tol in m/s) and it is at least 2% faster, so the
- * result is never slower than the default on this workload. The schedule is
+ * no certificate solve of its run stopped at the iteration cap (so every
+ * step reached the exact minimiser), every final position matches the
+ * default-schedule, widest-cap reference within steps * dt * tol (tol in
+ * m/s), and it is at least 2% faster, so the result is never slower than the
+ * default on this workload. The tuning runs use the tuner's own failure
+ * counters, not the context's. The schedule is
  * stored in the context (used by plans created afterwards with schedule NULL)
  * and returned in `out` (may be NULL). Allocates device scratch for the
  * workload; RS_ERR_OUT_OF_MEMORY if that fails.
@@ -336,7 +386,11 @@ rs_status rs_server_create(rs_ctx *ctx, const rs_params *p, int64_t hbm_budget_b
 rs_status rs_server_destroy(rs_server *s);
 /* Device bytes a request needs while admitted. */
 int64_t rs_request_bytes(int32_t envs, int32_t robots);
-/* Queue a request; returns RS_ERR_BUDGET if it can never fit. */
+/* Queue a request; returns RS_ERR_BUDGET if it can never fit. The id keys the
+ * request's streams (env id = id << 20 | env index), so ids are limited to
+ * 0..4095 (RS_ERR_INVALID_ARG otherwise) and requests that run at the same
+ * time need distinct ids; a long-running server recycles ids of finished
+ * requests, whose results then repeat for equal (id, envs, robots, horizon). */
 rs_status rs_server_submit(rs_server *s, int64_t id, int32_t envs, int32_t robots,
                            int32_t horizon);
 /* Run one tick: admit, launch, retire finished requests. *busy = 1 while any

@@ -41,6 +41,8 @@ struct rs_ctx {
   rs_schedule sched{};           // autotuned schedule table
   std::map<rs::GraphKey, rs::CachedGraph> graphs;  // rollout graph cache
   hipStream_t capture_stream = nullptr;
+  // certificate failures counted by the kernels: [0] infeasible, [1] capped
+  unsigned long long *qp_fail = nullptr;
 };
 
 struct rs_plan {

@@ -77,6 +77,8 @@ template <typename T> struct StepArgs {
   T *obs, *reward;
   uint8_t *done, *infeasible;
   float *maxviol;
+  int32_t *qp_stats;             // [E][kQPStats] accumulated (may be NULL)
+  unsigned long long *qp_fail;   // the context's failure counters
 };
 
 template <typename T, int G, bool PP>
@@ -111,8 +113,10 @@ __global__ __launch_bounds__(kBlock) void k_env_step(StepArgs<T> A) {
     A.episode[e] = episode;
     if (A.reward) A.reward[e] = out.reward;
     if (A.done) A.done[e] = out.done ? 1 : 0;
-    if (A.infeasible) A.infeasible[e] = out.qp.status == 1 ? 1 : 0;
+    if (A.infeasible) A.infeasible[e] = (uint8_t)out.qp.status;
     if (A.maxviol) A.maxviol[e] = (float)out.maxviol;
+    if (A.qp_stats) qp_stats_add(A.qp_stats + (size_t)e * kQPStats, out.qp);
+    qp_fail_count(A.qp_fail, out.qp);
   }
 }
 
@@ -164,6 +168,8 @@ template <typename T> struct BarrierArgs {
   T *ux, *uy, *lambda;
   float *maxviol;
   uint8_t *infeasible;
+  int32_t *qp_stats;
+  unsigned long long *qp_fail;
 };
 
 template <typename T, int G>
@@ -213,7 +219,11 @@ __global__ __launch_bounds__(kBlock) void k_barrier(BarrierArgs<T> A) {
                                       hiy);
     if (i == 0) A.maxviol[e] = (float)mv;
   }
-  if (A.infeasible && i == 0) A.infeasible[e] = info.status == 1 ? 1 : 0;
+  if (i == 0) {
+    if (A.infeasible) A.infeasible[e] = (uint8_t)info.status;
+    if (A.qp_stats) qp_stats_add(A.qp_stats + (size_t)e * kQPStats, info);
+    qp_fail_count(A.qp_fail, info);
+  }
 }
 
 template <typename K> static int blocks_for(int E, int G) {
@@ -256,9 +266,10 @@ static rs_status launch_status(const char *what) {
 }
 
 template <typename T>
-static rs_status do_env_step(const rs_params *p, const rs_batch *b, const uint8_t *actions,
-                             int64_t t_global, void *obs, void *reward, uint8_t *done,
-                             float *maxviol, uint8_t *infeasible, hipStream_t st) {
+static rs_status do_env_step(rs_ctx *ctx, const rs_params *p, const rs_batch *b,
+                             const uint8_t *actions, int64_t t_global, void *obs, void *reward,
+                             uint8_t *done, float *maxviol, uint8_t *infeasible,
+                             int32_t *qp_stats, hipStream_t st) {
   StepArgs<T> A;
   A.C = make_const<T>(*p);
   A.E = b->num_envs;
@@ -270,6 +281,8 @@ static rs_status do_env_step(const rs_params *p, const rs_batch *b, const uint8_
   A.actions = actions;
   A.obs = (T *)obs; A.reward = (T *)reward; A.done = done; A.infeasible = infeasible;
   A.maxviol = maxviol;
+  A.qp_stats = qp_stats;
+  A.qp_fail = ctx->qp_fail;
   const int G = pow2_group(A.N);
   if (p->scenario == RS_SCN_PREDATOR_PREY) {
     RS_DISPATCH_G(G, hipLaunchKernelGGL((k_env_step<T, GG, true>), dim3(blocks_for<T>(A.E, GG)),
@@ -305,9 +318,10 @@ static rs_status do_env_reset(const rs_params *p, const rs_batch *b, const uint8
 }
 
 template <typename T>
-static rs_status do_barrier(const rs_params *p, int E, int N, const void *px, const void *py,
-                            const void *uxn, const void *uyn, void *ux, void *uy, void *lambda,
-                            float *maxviol, uint8_t *infeasible, hipStream_t st) {
+static rs_status do_barrier(rs_ctx *ctx, const rs_params *p, int E, int N, const void *px,
+                            const void *py, const void *uxn, const void *uyn, void *ux, void *uy,
+                            void *lambda, float *maxviol, uint8_t *infeasible, int32_t *qp_stats,
+                            hipStream_t st) {
   BarrierArgs<T> A;
   A.C = make_const<T>(*p);
   A.E = E;
@@ -316,6 +330,8 @@ static rs_status do_barrier(const rs_params *p, int E, int N, const void *px, co
   A.ux = (T *)ux; A.uy = (T *)uy; A.lambda = (T *)lambda;
   A.maxviol = maxviol;
   A.infeasible = infeasible;
+  A.qp_stats = qp_stats;
+  A.qp_fail = ctx->qp_fail;
   const int G = pow2_group(N);
   RS_DISPATCH_G(G, hipLaunchKernelGGL((k_barrier<T, GG>), dim3(blocks_for<T>(E, GG)), dim3(kBlock),
                                       0, st, A));
@@ -393,6 +409,14 @@ rs_status rs_create(int device, rs_ctx **out) {
   rs_ctx *c = new rs_ctx();
   c->device = device;
   c->num_cus = prop.multiProcessorCount;
+  hipError_t he = hipMalloc((void **)&c->qp_fail, 2 * sizeof(unsigned long long));
+  if (he == hipSuccess) he = hipMemset(c->qp_fail, 0, 2 * sizeof(unsigned long long));
+  if (he != hipSuccess) {
+    if (c->qp_fail) (void)hipFree(c->qp_fail);
+    delete c;
+    set_error("context allocation failed: %s", hipGetErrorString(he));
+    return RS_ERR_DEVICE;
+  }
   c->sched.block_threads = 256;
   for (int n = 0; n <= RS_MAX_ROBOTS; ++n) c->sched.lanes_per_env[n] = 0;
   *out = c;
@@ -407,13 +431,26 @@ rs_status rs_destroy(rs_ctx *ctx) {
     (void)hipGraphDestroy(kv.second.graph);
   }
   if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
+  if (ctx->qp_fail) (void)hipFree(ctx->qp_fail);
   delete ctx;
+  return RS_OK;
+}
+
+rs_status rs_qp_failures(rs_ctx *ctx, int64_t *infeasible, int64_t *capped, int32_t reset) {
+  RS_CHECK_ARG(ctx != nullptr, "ctx is NULL");
+  RS_CHECK_HIP(hipSetDevice(ctx->device));
+  RS_CHECK_HIP(hipDeviceSynchronize());
+  unsigned long long h[2] = {0, 0};
+  RS_CHECK_HIP(hipMemcpy(h, ctx->qp_fail, sizeof(h), hipMemcpyDeviceToHost));
+  if (infeasible) *infeasible = (int64_t)h[0];
+  if (capped) *capped = (int64_t)h[1];
+  if (reset) RS_CHECK_HIP(hipMemset(ctx->qp_fail, 0, sizeof(h)));
   return RS_OK;
 }
 
 rs_status env_step(rs_ctx *ctx, const rs_params *p, const rs_batch *b, const uint8_t *actions,
                    int64_t t_global, void *obs, void *reward, uint8_t *done, float *max_violation,
-                   uint8_t *infeasible, void *stream) {
+                   uint8_t *infeasible, int32_t *qp_stats, void *stream) {
   RS_CHECK_ARG(ctx != nullptr, "ctx is NULL");
   rs_status s = check_params(p);
   if (s != RS_OK) return s;
@@ -421,10 +458,10 @@ rs_status env_step(rs_ctx *ctx, const rs_params *p, const rs_batch *b, const uin
   if (s != RS_OK) return s;
   hipStream_t st = (hipStream_t)stream;
   if (p->dtype == RS_F64)
-    return do_env_step<double>(p, b, actions, t_global, obs, reward, done, max_violation,
-                               infeasible, st);
-  return do_env_step<float>(p, b, actions, t_global, obs, reward, done, max_violation, infeasible,
-                            st);
+    return do_env_step<double>(ctx, p, b, actions, t_global, obs, reward, done, max_violation,
+                               infeasible, qp_stats, st);
+  return do_env_step<float>(ctx, p, b, actions, t_global, obs, reward, done, max_violation,
+                            infeasible, qp_stats, st);
 }
 
 rs_status env_reset(rs_ctx *ctx, const rs_params *p, const rs_batch *b, const uint8_t *mask,
@@ -442,7 +479,8 @@ rs_status env_reset(rs_ctx *ctx, const rs_params *p, const rs_batch *b, const ui
 rs_status barrier_certificate(rs_ctx *ctx, const rs_params *p, int32_t num_envs, int32_t robots,
                               const void *px, const void *py, const void *ux_nom,
                               const void *uy_nom, void *ux, void *uy, void *lambda,
-                              float *max_violation, uint8_t *infeasible, void *stream) {
+                              float *max_violation, uint8_t *infeasible, int32_t *qp_stats,
+                              void *stream) {
   RS_CHECK_ARG(ctx != nullptr, "ctx is NULL");
   rs_status s = check_params(p);
   if (s != RS_OK) return s;
@@ -454,10 +492,10 @@ rs_status barrier_certificate(rs_ctx *ctx, const rs_params *p, int32_t num_envs,
   for (const void *q : ps) RS_CHECK_ARG((uintptr_t)q % a == 0, "misaligned array");
   hipStream_t st = (hipStream_t)stream;
   if (p->dtype == RS_F64)
-    return do_barrier<double>(p, num_envs, robots, px, py, ux_nom, uy_nom, ux, uy, lambda,
-                              max_violation, infeasible, st);
-  return do_barrier<float>(p, num_envs, robots, px, py, ux_nom, uy_nom, ux, uy, lambda,
-                           max_violation, infeasible, st);
+    return do_barrier<double>(ctx, p, num_envs, robots, px, py, ux_nom, uy_nom, ux, uy, lambda,
+                              max_violation, infeasible, qp_stats, st);
+  return do_barrier<float>(ctx, p, num_envs, robots, px, py, ux_nom, uy_nom, ux, uy, lambda,
+                           max_violation, infeasible, qp_stats, st);
 }
 
 }  // extern "C"

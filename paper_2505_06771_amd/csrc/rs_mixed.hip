@@ -41,10 +41,11 @@ __device__ void run_tile(const RunArgs &A, char *wave_lds, int lane, int first, 
 
   float x = 0.f, y = 0.f, th = 0.f, gx = 0.f, gy = 0.f;
   int step = A.step[e], episode = A.episode[e];
-  if (A.reset_mask && A.reset_mask[e]) {
+  const bool consume = !A.reset_all && !A.reset_only && A.reset_mask && A.reset_mask[e];
+  if (A.reset_all || (A.reset_only && A.reset_only[e]) || consume) {
     reset_env<float, G, PP>(K, env_id, (uint32_t)episode, i, N, lane, x, y, th, gx, gy);
     step = 0;
-    if (i == 0) A.reset_mask[e] = 0;
+    if (consume && i == 0) A.reset_mask[e] = 0;
   } else if (on) {
     x = A.x[r]; y = A.y[r]; th = A.th[r]; gx = A.gx[r]; gy = A.gy[r];
   }
@@ -67,6 +68,8 @@ __device__ void run_tile(const RunArgs &A, char *wave_lds, int lane, int first, 
     if (i == 0) {
       if (A.reward_out) A.reward_out[(size_t)k * A.E + e] = so.reward;
       if (A.done_out) A.done_out[(size_t)k * A.E + e] = so.done ? 1 : 0;
+      if (A.qp_stats) qp_stats_add(A.qp_stats + (size_t)e * kQPStats, so.qp);
+      qp_fail_count(A.qp_fail, so.qp);
     }
   }
   if (on) { A.x[r] = x; A.y[r] = y; A.th[r] = th; A.gx[r] = gx; A.gy[r] = gy; }
@@ -184,6 +187,7 @@ static RunArgs plan_args(const rs_plan *pl, const rs_params *p, const rs_batch *
   A.x = (float *)b->x; A.y = (float *)b->y; A.th = (float *)b->theta;
   A.gx = (float *)b->goal_x; A.gy = (float *)b->goal_y;
   A.step = b->step; A.episode = b->episode;
+  A.qp_fail = pl->ctx->qp_fail;
   for (int n = 0; n <= RS_MAX_ROBOTS; ++n)
     A.qp_iters[n] = pl->sched.qp_iters[n] > 0 ? pl->sched.qp_iters[n] : p->qp_max_iters;
   return A;
@@ -298,18 +302,11 @@ rs_status env_reset_mixed(rs_ctx *ctx, const rs_params *p, const rs_plan *plan, 
   if (s != RS_OK) return s;
   RunArgs A = plan_args(plan, p, b);
   A.steps = 0;
-  // the kernel clears the flags it consumes: work on a scratch copy
-  uint8_t *flags = nullptr;
-  hipStream_t st = (hipStream_t)stream;
-  RS_CHECK_HIP(hipMallocAsync((void **)&flags, plan->num_envs, st));
-  if (mask) {
-    RS_CHECK_HIP(hipMemcpyAsync(flags, mask, plan->num_envs, hipMemcpyDeviceToDevice, st));
-  } else {
-    RS_CHECK_HIP(hipMemsetAsync(flags, 1, plan->num_envs, st));
-  }
-  A.reset_mask = flags;
-  hipError_t he = launch_run(A, plan->block_threads, st);
-  (void)hipFreeAsync(flags, st);
+  // the caller's mask is only read (no flag is consumed), so nothing is
+  // allocated or copied
+  A.reset_only = mask;
+  A.reset_all = mask ? 0 : 1;
+  hipError_t he = launch_run(A, plan->block_threads, (hipStream_t)stream);
   if (he != hipSuccess) {
     set_error("env_reset_mixed launch failed: %s", hipGetErrorString(he));
     return RS_ERR_DEVICE;
@@ -317,14 +314,22 @@ rs_status env_reset_mixed(rs_ctx *ctx, const rs_params *p, const rs_plan *plan, 
   return RS_OK;
 }
 
-rs_status env_run(rs_ctx *ctx, const rs_params *p, const rs_plan *plan, const rs_batch *b,
-                  int32_t steps, const int64_t *t_start, int64_t t_global0,
-                  const int32_t *steps_per_env, float *reward_out, uint8_t *done_out,
-                  float *reward_sum, float *obs_final, void *stream) {
+}  // extern "C"
+
+namespace rs {
+
+// env_run with the failure counters it adds to (the context's, or the
+// autotuner's own).
+static rs_status run_plan(rs_ctx *ctx, const rs_params *p, const rs_plan *plan, const rs_batch *b,
+                          int32_t steps, const int64_t *t_start, int64_t t_global0,
+                          const int32_t *steps_per_env, float *reward_out, uint8_t *done_out,
+                          float *reward_sum, float *obs_final, int32_t *qp_stats,
+                          unsigned long long *fail, void *stream) {
   rs_status s = check_mixed(ctx, p, plan, b);
   if (s != RS_OK) return s;
   RS_CHECK_ARG(steps >= 0, "steps must be >= 0");
   RunArgs A = plan_args(plan, p, b);
+  A.qp_fail = fail;
   A.steps = steps;
   A.t0 = (uint32_t)t_global0;
   A.t_start = t_start;
@@ -334,12 +339,29 @@ rs_status env_run(rs_ctx *ctx, const rs_params *p, const rs_plan *plan, const rs
   A.reward_sum = reward_sum;
   A.obs_final = obs_final;
   A.obs_off = plan->obs_off_dev;
+  A.qp_stats = qp_stats;
   hipError_t he = launch_run(A, plan->block_threads, (hipStream_t)stream);
   if (he != hipSuccess) {
     set_error("env_run launch failed: %s", hipGetErrorString(he));
     return RS_ERR_DEVICE;
   }
   return RS_OK;
+}
+
+}  // namespace rs
+
+extern "C" {
+
+rs_status env_run(rs_ctx *ctx, const rs_params *p, const rs_plan *plan, const rs_batch *b,
+                  int32_t steps, const int64_t *t_start, int64_t t_global0,
+                  const int32_t *steps_per_env, float *reward_out, uint8_t *done_out,
+                  float *reward_sum, float *obs_final, int32_t *qp_stats, void *stream) {
+  if (ctx == nullptr) {
+    set_error("ctx/plan/batch is NULL");
+    return RS_ERR_INVALID_ARG;
+  }
+  return run_plan(ctx, p, plan, b, steps, t_start, t_global0, steps_per_env, reward_out,
+                  done_out, reward_sum, obs_final, qp_stats, ctx->qp_fail, stream);
 }
 
 rs_status rs_get_schedule(rs_ctx *ctx, rs_schedule *out) {
@@ -381,7 +403,7 @@ rs_status rs_autotune(rs_ctx *ctx, const rs_params *p, const int32_t *robots, in
   int32_t *ibuf = nullptr;
   rs_status result = RS_OK;
   if (hipMalloc(&dbuf, 10 * R * sizeof(float)) != hipSuccess ||
-      hipMalloc(&ibuf, 2 * (size_t)E * sizeof(int32_t)) != hipSuccess) {
+      hipMalloc(&ibuf, (2 * (size_t)E + 4) * sizeof(int32_t)) != hipSuccess) {
     set_error("autotune allocation failed");
     result = RS_ERR_OUT_OF_MEMORY;
   }
@@ -393,7 +415,12 @@ rs_status rs_autotune(rs_ctx *ctx, const rs_params *p, const int32_t *robots, in
     (void)hipMemcpyAsync(dbuf, init, 5 * R * 4, hipMemcpyDeviceToDevice, st);
     (void)hipMemsetAsync(ibuf, 0, 2 * (size_t)E * sizeof(int32_t), st);
   };
-  // run `sched` (min over reps) and check it against the reference positions
+  // the tuner's own failure counters ([0] infeasible, [1] capped solves),
+  // behind the env flags
+  unsigned long long *fail = ibuf ? reinterpret_cast<unsigned long long *>(ibuf + 2 * E) : nullptr;
+  // run `sched` (min over reps); a candidate passes when no certificate of
+  // its first run stopped at the iteration cap (every step then reached the
+  // exact minimiser) and its final positions match the reference
   auto measure = [&](const rs_schedule &sched, bool check, float &ms) -> bool {
     rs_plan *pl = nullptr;
     if (rs_plan_create(ctx, E, counts.data(), &sched, &pl) != RS_OK) return false;
@@ -401,9 +428,10 @@ rs_status rs_autotune(rs_ctx *ctx, const rs_params *p, const int32_t *robots, in
     bool ok = true;
     for (int rep = 0; rep < 3 && ok; ++rep) {
       restore();
+      if (rep == 0) (void)hipMemsetAsync(fail, 0, 2 * sizeof(unsigned long long), st);
       (void)hipEventRecord(ev0, st);
-      if (env_run(ctx, p, pl, &b, steps, nullptr, 0, nullptr, nullptr, nullptr, nullptr, nullptr,
-                  st) != RS_OK) {
+      if (run_plan(ctx, p, pl, &b, steps, nullptr, 0, nullptr, nullptr, nullptr, nullptr, nullptr,
+                   nullptr, fail, st) != RS_OK) {
         ok = false;
         break;
       }
@@ -412,7 +440,12 @@ rs_status rs_autotune(rs_ctx *ctx, const rs_params *p, const int32_t *robots, in
       float t = 0.f;
       (void)hipEventElapsedTime(&t, ev0, ev1);
       ms = std::min(ms, t);
-      if (rep == 0 && check) {
+      if (rep == 0) {
+        unsigned long long h[2] = {0, 0};
+        (void)hipMemcpy(h, fail, sizeof(h), hipMemcpyDeviceToHost);
+        ok = h[1] == 0;
+      }
+      if (ok && rep == 0 && check) {
         (void)hipMemcpy(cx.data(), b.x, R * 4, hipMemcpyDeviceToHost);
         (void)hipMemcpy(cy.data(), b.y, R * 4, hipMemcpyDeviceToHost);
         const double bound = steps * p->dt * tol;
@@ -471,6 +504,8 @@ rs_status rs_autotune(rs_ctx *ctx, const rs_params *p, const int32_t *robots, in
       (void)hipMemcpy(rx.data(), b.x, R * 4, hipMemcpyDeviceToHost);
       (void)hipMemcpy(ry.data(), b.y, R * 4, hipMemcpyDeviceToHost);
     } else if (result == RS_OK) {
+      set_error("autotune: the reference run failed or a certificate reached the widest "
+                "iteration cap (8N+32)");
       result = RS_ERR_DEVICE;
     }
     // coordinate descent from the default schedule: block size, then lanes

@@ -120,12 +120,42 @@ __device__ __forceinline__ T gram_entry(int as, int bs, T dxs, T dys, int at, in
   return acc;
 }
 
+// Stage of the solver that produced the command.
+enum : int {
+  kStBox = 0,        // no row violated at the box clip u0
+  kStOneRow = 1,     // one violated row: closed-form projection
+  kStTwoRows = 2,    // two violated rows on four distinct robots
+  kStShared = 3,     // two violated rows through a shared robot (2 x 2 Gram system)
+  kStActiveSet = 4,  // register-resident active-set loop
+  kStGeneral = 5     // general active-set solver with its rows in LDS
+};
+
 struct QPInfo {
   int status;  // 0 solved, 1 infeasible, 2 iteration cap / numerical failure
   int iters;   // active-set iterations
   int q;       // active pairwise rows at exit
   int in_lds;  // 1: the rows are in sh->act / sh->lam (general solver)
+  int stage;   // kSt*: the stage that produced the command
 };
+
+// Per-env certificate statistics (the qp_stats outputs): slots 0..5 count
+// solves by the stage that produced the command, slot 6 infeasible solves,
+// slot 7 solves stopped by the iteration cap or a numerical failure (neither
+// of the last two is counted in 0..5), slot 8 the active-set iterations of
+// the solves that ran the loop.
+constexpr int kQPStats = 9;
+__device__ __forceinline__ int qp_stat_slot(const QPInfo &q) {
+  return q.status == 1 ? 6 : (q.status == 2 ? 7 : q.stage);
+}
+// Adds one solve to an env's counters (one lane of the group calls it).
+__device__ __forceinline__ void qp_stats_add(int32_t *q, const QPInfo &info) {
+  q[qp_stat_slot(info)] += 1;
+  if (info.stage >= kStActiveSet) q[8] += info.iters;
+}
+// Always-on failure counters of a context: [0] infeasible, [1] capped.
+__device__ __forceinline__ void qp_fail_count(unsigned long long *fail, const QPInfo &info) {
+  if (fail && info.status != 0) atomicAdd(fail + (info.status - 1), 1ull);
+}
 
 // General solver with the active set in LDS (any number of active rows).
 // Every lane of the group must call this together (uniform control flow
@@ -138,7 +168,7 @@ __device__ QPInfo qp_solve_lds(QPScratch<T, G> *sh, const SimConst<T> C, int lan
                            T &uy) {
   const int base = lane & ~(G - 1);
   const T BIG = big_v<T>();
-  QPInfo info{0, 0, 0, 1};
+  QPInfo info{0, 0, 0, 1, kStGeneral};
 
   // --- empty box: infeasible, closed-form fallback -------------------------
   const bool crossed = on && (lox > hix || loy > hiy);
@@ -518,7 +548,7 @@ __device__ __noinline__ QPLoopOut<T> qp_active_set(QPScratch<T, G> *sh, int lane
   // the wavefronts in this loop are the slowest of a launch: give them the
   // first claim on issue slots over the other wavefront of their SIMD
   __builtin_amdgcn_s_setprio(1);
-  QPInfo info{0, 0, 0, 0};
+  QPInfo info{0, 0, 0, 0, kStBox};
   bool dead = false;
   T ux, uy;
   // --- geometry of the owned pairs ------------------------------------------
@@ -875,7 +905,7 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
   const auto &C = *K.get();  // the solver's constants, loaded for this phase
   constexpr int KH = G / 2;
   const T BIG = big_v<T>();
-  QPInfo info{0, 0, 0, 0};
+  QPInfo info{0, 0, 0, 0, kStBox};
 
   // --- box clip u0 (every bound holds there) ---------------------------------
   ux = uhx;
@@ -1138,6 +1168,7 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
       ux = (accept || seeded) ? nux : ux;
       uy = (accept || seeded) ? nuy : uy;
       fq = accept ? (two ? 2 : 1) : fq;
+      info.stage = two ? (shared ? kStShared : kStTwoRows) : kStOneRow;
       seed = seeded;
       fpa = pa; fpb = pb; fl1 = lam1; fdx = bdx; fdy = bdy;
       fqa = qa; fqb = qb; fl2 = lam2;
@@ -1157,6 +1188,7 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
     info.iters = r.iters;
     info.q = r.q;
     info.in_lds = r.in_lds;
+    info.stage = r.in_lds ? kStGeneral : kStActiveSet;
     if (act_out) {
       act_out->q = r.q;
 #pragma unroll
@@ -1170,6 +1202,7 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
   }
   if (dead) {
     info.status = 1;
+    info.stage = kStBox;
     fq = 0;
     if (on) {
       ux = lox <= hix ? tmin(tmax(uhx, lox), hix) : T(0.5) * (lox + hix);

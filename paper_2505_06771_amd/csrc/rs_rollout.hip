@@ -48,6 +48,8 @@ struct RolloutArgs {
   uint8_t *actions;
   float *reward;
   uint8_t *done;
+  int32_t *qp_stats;            // [E][kQPStats] accumulated (STATS kernels only)
+  unsigned long long *qp_fail;  // the context's failure counters
 };
 
 __device__ __forceinline__ void wave_lds_sync() {
@@ -90,8 +92,9 @@ __device__ __forceinline__ int perm_hidden(int s, int g, int j) {
 }
 
 // NC > 0 fixes the robot count at compile time (NC <= G); NC = 0 reads it
-// from the arguments.
-template <int G, int NC, bool PP>
+// from the arguments. STATS: the kernel also counts the certificate's stages
+// per env (qp_stats); the kernels without it carry none of that code.
+template <int G, int NC, bool PP, bool STATS>
 __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
   constexpr int EPW = 64 / G;
   __shared__ QPScratch<float, G> qs[kRollBlock / G];
@@ -359,6 +362,8 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
       if (i == 0) {
         (A.reward + (size_t)t * A.E)[(uint32_t)e] = so.reward;
         (A.done + (size_t)t * A.E)[(uint32_t)e] = so.done ? 1 : 0;
+        if constexpr (STATS) qp_stats_add(A.qp_stats + (size_t)e * kQPStats, so.qp);
+        qp_fail_count(A.qp_fail, so.qp);
       }
     }
   }
@@ -369,19 +374,20 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
 // Kernel for N robots: a compile-time robot count for N = 8 (8 lanes, no
 // idle lane) and N = 3 (the team size of the paper's scenarios), the
 // lane-group width with a run-time count otherwise.
-template <bool PP> static const void *rollout_kernel_for(int N) {
-  if (N == 8) return reinterpret_cast<const void *>(&k_rollout<8, 8, PP>);
-  if (N == 3) return reinterpret_cast<const void *>(&k_rollout<4, 3, PP>);  // the paper's teams
+template <bool PP, bool ST> static const void *rollout_kernel_for(int N) {
+  if (N == 8) return reinterpret_cast<const void *>(&k_rollout<8, 8, PP, ST>);
+  if (N == 3) return reinterpret_cast<const void *>(&k_rollout<4, 3, PP, ST>);  // the paper's teams
   switch (pow2_group(N)) {
-    case 2: return reinterpret_cast<const void *>(&k_rollout<2, 0, PP>);
-    case 4: return reinterpret_cast<const void *>(&k_rollout<4, 0, PP>);
-    case 8: return reinterpret_cast<const void *>(&k_rollout<8, 0, PP>);
-    default: return reinterpret_cast<const void *>(&k_rollout<16, 0, PP>);
+    case 2: return reinterpret_cast<const void *>(&k_rollout<2, 0, PP, ST>);
+    case 4: return reinterpret_cast<const void *>(&k_rollout<4, 0, PP, ST>);
+    case 8: return reinterpret_cast<const void *>(&k_rollout<8, 0, PP, ST>);
+    default: return reinterpret_cast<const void *>(&k_rollout<16, 0, PP, ST>);
   }
 }
 static const void *rollout_kernel(const RolloutArgs &A) {
-  return A.C.scenario == RS_SCN_PREDATOR_PREY ? rollout_kernel_for<true>(A.N)
-                                              : rollout_kernel_for<false>(A.N);
+  const bool pp = A.C.scenario == RS_SCN_PREDATOR_PREY, st = A.qp_stats != nullptr;
+  if (pp) return st ? rollout_kernel_for<true, true>(A.N) : rollout_kernel_for<true, false>(A.N);
+  return st ? rollout_kernel_for<false, true>(A.N) : rollout_kernel_for<false, false>(A.N);
 }
 
 static bool launch_rollout(const RolloutArgs &A, dim3 grid, hipStream_t st) {
@@ -397,7 +403,7 @@ using namespace rs;
 extern "C" rs_status rollout(rs_ctx *ctx, const rs_params *p, const rs_batch *b,
                              const rs_policy *policy, int32_t horizon, int64_t t_global0,
                              float *obs, uint8_t *actions, float *reward, uint8_t *done,
-                             void *stream) {
+                             int32_t *qp_stats, void *stream) {
   RS_CHECK_ARG(ctx != nullptr, "ctx is NULL");
   rs_status s = check_params(p);
   if (s != RS_OK) return s;
@@ -432,6 +438,8 @@ extern "C" rs_status rollout(rs_ctx *ctx, const rs_params *p, const rs_batch *b,
   A.w3 = (const __bf16 *)policy->w3;
   A.b1 = policy->b1; A.b2 = policy->b2; A.b3 = policy->b3;
   A.obs = obs; A.actions = actions; A.reward = reward; A.done = done;
+  A.qp_stats = qp_stats;
+  A.qp_fail = ctx->qp_fail;
   const int G = pow2_group(A.N);
   const int waves = (A.E + (64 / G) - 1) / (64 / G);
   const dim3 grid((waves + kRollWaves - 1) / kRollWaves);

@@ -26,6 +26,8 @@ struct RunArgs {
   const int32_t *steps_per_env;  // [E] step budget (NULL: steps)
   int32_t *steps_left_after;     // [E] written: budget - steps run (may be NULL)
   uint8_t *reset_mask;     // [E] reset (and clear) flagged envs first (may be NULL)
+  const uint8_t *reset_only;  // [E] reset flagged envs, flags left as they are (may be NULL)
+  int reset_all;           // reset every env first
   float *x, *y, *th, *gx, *gy;
   int32_t *step, *episode;
   float *reward_out;       // [steps][E] (may be NULL)
@@ -33,6 +35,8 @@ struct RunArgs {
   float *reward_sum;       // [E] accumulated (may be NULL)
   float *obs_final;        // (may be NULL)
   const int64_t *obs_off;  // [E] offsets into obs_final
+  int32_t *qp_stats;       // [E][kQPStats] accumulated (may be NULL)
+  unsigned long long *qp_fail;  // the context's failure counters
   int32_t qp_iters[17];
 };
 

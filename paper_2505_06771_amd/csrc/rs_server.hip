@@ -12,7 +12,10 @@
 // the host while the current one runs; at most two ticks are in flight. The
 // host knows each request's remaining steps, so a request whose last step is
 // in tick k is retired as soon as tick k's event completes: its final poses
-// and summed rewards are copied out and its ranges are freed.
+// and summed rewards are copied out and its ranges are freed. Admission and
+// retirement allocate no device or pinned memory and create no events: slot
+// metadata is staged in a pinned table indexed like the slot table, and a
+// request only remembers the index of its last tick.
 //
 // Determinism: an env's stream id is (request id << 20 | env index) and its
 // stream time is its own step count, so a request's result does not depend on
@@ -78,8 +81,7 @@ struct Request {
   int64_t slot_off = -1;
   int64_t bytes = 0;
   double submit_t = 0, admit_t = 0, finish_t = 0;
-  hipEvent_t last_tick = nullptr;  // recorded after the tick holding its last step
-  int32_t *meta = nullptr;         // pinned staging of its slot metadata
+  int64_t last_tick = -1;  // index of the tick holding its last step
   std::vector<float> xy, rsum;
 };
 
@@ -105,6 +107,7 @@ struct rs_server {
   int32_t *items_dev[2] = {nullptr, nullptr};
   int32_t *tiles_host[2] = {nullptr, nullptr};  // pinned staging
   int32_t *items_host[2] = {nullptr, nullptr};
+  int32_t *meta_host = nullptr;  // pinned [4][cap_slots]: nrob, offset, steps, env id per slot
   hipEvent_t staging_free[2] = {nullptr, nullptr};
   int cur = 0;
   std::vector<int32_t> nrob_of;  // host mirror of nrob per slot
@@ -112,8 +115,9 @@ struct rs_server {
   std::deque<std::unique_ptr<Request>> queue;
   std::vector<std::unique_ptr<Request>> running;
   std::deque<std::unique_ptr<Request>> finished;
-  hipEvent_t tick_ev[2] = {nullptr, nullptr};  // flow control: ticks k-1, k-2
+  hipEvent_t tick_ev[2] = {nullptr, nullptr};  // event of tick k in slot k & 1
   int64_t ticks_launched = 0;
+  int64_t ticks_done = 0;  // ticks 0 .. ticks_done - 1 are known complete
   hipStream_t stream = nullptr, copy_stream = nullptr;
   rs_server_stats stats{};
 };
@@ -136,28 +140,32 @@ static void free_server(rs_server *s) {
   }
   for (hipEvent_t e : s->tick_ev)
     if (e) (void)hipEventDestroy(e);
-  for (auto &r : s->running) {
-    if (r->last_tick) (void)hipEventDestroy(r->last_tick);
-    if (r->meta) (void)hipHostFree(r->meta);
-  }
+  if (s->meta_host) (void)hipHostFree(s->meta_host);
   if (s->stream) (void)hipStreamDestroy(s->stream);
   if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
   delete s;
+}
+
+// Whether tick k has completed (ticks complete in launch order on the one
+// stream). The event of tick k stays in slot k & 1 until tick k + 2 is
+// launched, and launching tick k + 2 first waits for tick k.
+static bool tick_complete(rs_server *s, int64_t k, bool wait) {
+  if (k < s->ticks_done) return true;
+  if (k >= s->ticks_launched) return false;
+  hipEvent_t ev = s->tick_ev[k & 1];
+  if ((wait ? hipEventSynchronize(ev) : hipEventQuery(ev)) != hipSuccess) return false;
+  s->ticks_done = k + 1;
+  return true;
 }
 
 // Retire requests whose last tick has completed.
 static rs_status retire(rs_server *s, bool wait) {
   for (size_t k = 0; k < s->running.size();) {
     Request *r = s->running[k].get();
-    bool ready = false;
-    if (r->remaining == 0 && r->last_tick) {
-      hipError_t q = wait ? hipEventSynchronize(r->last_tick) : hipEventQuery(r->last_tick);
-      ready = q == hipSuccess;
-    }
+    const bool ready = r->remaining == 0 && r->last_tick >= 0 && tick_complete(s, r->last_tick, wait);
     if (!ready) { ++k; continue; }
     const int64_t R = (int64_t)r->envs * r->robots;
     std::vector<float> hx(R), hy(R);
-    RS_CHECK_HIP(hipStreamWaitEvent(s->copy_stream, r->last_tick, 0));
     RS_CHECK_HIP(hipMemcpyAsync(hx.data(), s->x + r->robot_off, R * 4, hipMemcpyDeviceToHost, s->copy_stream));
     RS_CHECK_HIP(hipMemcpyAsync(hy.data(), s->y + r->robot_off, R * 4, hipMemcpyDeviceToHost, s->copy_stream));
     r->rsum.resize(r->envs);
@@ -170,10 +178,6 @@ static rs_status retire(rs_server *s, bool wait) {
     s->robots_alloc.release(r->robot_off, R);
     s->slots_alloc.release(r->slot_off, r->envs);
     s->in_use -= r->bytes;
-    (void)hipEventDestroy(r->last_tick);
-    r->last_tick = nullptr;
-    (void)hipHostFree(r->meta);
-    r->meta = nullptr;
     s->stats.finished++;
     s->finished.push_back(std::move(s->running[k]));
     s->running.erase(s->running.begin() + k);
@@ -200,21 +204,24 @@ static rs_status admit(rs_server *s) {
     s->in_use += r->bytes;
     s->peak = std::max(s->peak, s->in_use);
     // slot metadata: nrob, offset, steps_left, env_ids (4 int32 per env),
-    // staged in pinned memory that lives until the request retires
-    RS_CHECK_HIP(hipHostMalloc((void **)&r->meta, (size_t)r->envs * 16, hipHostMallocDefault));
-    int32_t *m = r->meta;
+    // staged in the pinned table at the request's slots. A slot range is
+    // handed out again only after its previous request retired, i.e. after
+    // the tick holding its last step completed, which the copies below of
+    // that request preceded on the same stream.
+    const int64_t S = s->cap_slots;
+    int32_t *m0 = s->meta_host + so, *m1 = m0 + S, *m2 = m1 + S, *m3 = m2 + S;
     for (int32_t e = 0; e < r->envs; ++e) {
-      m[e] = r->robots;
-      m[r->envs + e] = (int32_t)(ro + (int64_t)e * r->robots);
-      m[2 * r->envs + e] = r->horizon;
-      m[3 * r->envs + e] = (int32_t)(((uint32_t)r->id << 20) | (uint32_t)e);
+      m0[e] = r->robots;
+      m1[e] = (int32_t)(ro + (int64_t)e * r->robots);
+      m2[e] = r->horizon;
+      m3[e] = (int32_t)(((uint32_t)r->id << 20) | (uint32_t)e);
       s->nrob_of[so + e] = r->robots;
     }
     const size_t nb = (size_t)r->envs * 4;
-    RS_CHECK_HIP(hipMemcpyAsync(s->nrob + so, m, nb, hipMemcpyHostToDevice, s->stream));
-    RS_CHECK_HIP(hipMemcpyAsync(s->offset + so, m + r->envs, nb, hipMemcpyHostToDevice, s->stream));
-    RS_CHECK_HIP(hipMemcpyAsync(s->steps_left + so, m + 2 * r->envs, nb, hipMemcpyHostToDevice, s->stream));
-    RS_CHECK_HIP(hipMemcpyAsync(s->env_ids + so, m + 3 * r->envs, nb, hipMemcpyHostToDevice, s->stream));
+    RS_CHECK_HIP(hipMemcpyAsync(s->nrob + so, m0, nb, hipMemcpyHostToDevice, s->stream));
+    RS_CHECK_HIP(hipMemcpyAsync(s->offset + so, m1, nb, hipMemcpyHostToDevice, s->stream));
+    RS_CHECK_HIP(hipMemcpyAsync(s->steps_left + so, m2, nb, hipMemcpyHostToDevice, s->stream));
+    RS_CHECK_HIP(hipMemcpyAsync(s->env_ids + so, m3, nb, hipMemcpyHostToDevice, s->stream));
     RS_CHECK_HIP(hipMemsetAsync(s->t_next + so, 0, (size_t)r->envs * 8, s->stream));
     RS_CHECK_HIP(hipMemsetAsync(s->step + so, 0, nb, s->stream));
     RS_CHECK_HIP(hipMemsetAsync(s->episode + so, 0, nb, s->stream));
@@ -236,7 +243,10 @@ static rs_status launch_tick(rs_server *s) {
   if (envs.empty()) return RS_OK;
   // at most two ticks in flight: wait for tick k-2 before launching tick k
   const int slot = (int)(s->ticks_launched & 1);
-  if (s->ticks_launched >= 2) RS_CHECK_HIP(hipEventSynchronize(s->tick_ev[slot]));
+  if (s->ticks_launched >= 2 && !tick_complete(s, s->ticks_launched - 2, true)) {
+    set_error("serving: waiting for tick %lld failed", (long long)(s->ticks_launched - 2));
+    return RS_ERR_DEVICE;
+  }
   std::vector<int32_t> tiles, items;
   build_tiles(envs, s->nrob_of, s->ctx->sched, tiles, items);
   const int k = s->cur;
@@ -268,7 +278,10 @@ static rs_status launch_tick(rs_server *s) {
   A.x = s->x; A.y = s->y; A.th = s->th; A.gx = s->gx; A.gy = s->gy;
   A.step = s->step; A.episode = s->episode;
   A.reward_sum = s->rsum;
-  for (int n = 0; n <= RS_MAX_ROBOTS; ++n) A.qp_iters[n] = s->ctx->sched.qp_iters[n];
+  A.qp_fail = s->ctx->qp_fail;
+  // the iteration cap of env_run's plans: the schedule's, else the parameters'
+  for (int n = 0; n <= RS_MAX_ROBOTS; ++n)
+    A.qp_iters[n] = s->ctx->sched.qp_iters[n] > 0 ? s->ctx->sched.qp_iters[n] : s->p.qp_max_iters;
   const int blk = s->ctx->sched.block_threads > 0 ? s->ctx->sched.block_threads : 256;
   hipError_t he = launch_run(A, blk, s->stream);
   if (he != hipSuccess) {
@@ -276,16 +289,13 @@ static rs_status launch_tick(rs_server *s) {
     return RS_ERR_DEVICE;
   }
   RS_CHECK_HIP(hipEventRecord(s->tick_ev[slot], s->stream));
-  s->ticks_launched++;
+  const int64_t this_tick = s->ticks_launched++;
   for (auto &r : s->running) {
     if (r->remaining <= 0) continue;
     const int32_t adv = std::min(r->remaining, s->tick_steps);
     s->stats.robot_steps += (int64_t)adv * r->envs * r->robots;
     r->remaining -= adv;
-    if (r->remaining == 0) {
-      RS_CHECK_HIP(hipEventCreateWithFlags(&r->last_tick, hipEventDisableTiming));
-      RS_CHECK_HIP(hipEventRecord(r->last_tick, s->stream));
-    }
+    if (r->remaining == 0) r->last_tick = this_tick;
   }
   s->stats.ticks++;
   return RS_OK;
@@ -346,6 +356,8 @@ rs_status rs_server_create(rs_ctx *ctx, const rs_params *p, int64_t hbm_budget_b
       return fail("pinned staging");
     if (hipEventCreateWithFlags(&s->staging_free[k], hipEventDisableTiming)) return fail("event");
   }
+  if (hipHostMalloc((void **)&s->meta_host, 4 * S * sizeof(int32_t), hipHostMallocDefault))
+    return fail("pinned metadata table");
   if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) ||
       hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking))
     return fail("streams");

@@ -18,6 +18,9 @@ LIB_PATH = os.path.join(_PKG, "librobostep.so")
 RS_F32, RS_F64 = 0, 1
 RS_CTRL_DISCRETE, RS_CTRL_GOTO, RS_CTRL_WAYPOINT = 0, 1, 2
 RS_SCN_NAVIGATION, RS_SCN_PREDATOR_PREY = 0, 1
+# certificate statistics (qp_stats slots)
+QPS_BOX, QPS_ONE_ROW, QPS_TWO_ROWS, QPS_SHARED_ROBOT, QPS_ACTIVE_SET, QPS_GENERAL = range(6)
+QPS_INFEASIBLE, QPS_CAPPED, QPS_ITERATIONS, QPS_COUNT = 6, 7, 8, 9
 STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "out of memory",
           4: "device error", 5: "over budget", 6: "not found"}
 
@@ -108,11 +111,13 @@ def lib():
         "rs_create": (i32, [ctypes.c_int, P(_VP)]),
         "rs_destroy": (i32, [_VP]),
         "env_reset": (i32, [_VP, P(RsParams), P(RsBatch), _VP, _VP, _VP]),
-        "env_step": (i32, [_VP, P(RsParams), P(RsBatch), _VP, i64, _VP, _VP, _VP, _VP, _VP, _VP]),
+        "rs_qp_failures": (i32, [_VP, P(i64), P(i64), i32]),
+        "env_step": (i32, [_VP, P(RsParams), P(RsBatch), _VP, i64, _VP, _VP, _VP, _VP, _VP, _VP,
+                           _VP]),
         "barrier_certificate": (i32, [_VP, P(RsParams), i32, i32, _VP, _VP, _VP, _VP, _VP, _VP,
-                                      _VP, _VP, _VP, _VP]),
+                                      _VP, _VP, _VP, _VP, _VP]),
         "rollout": (i32, [_VP, P(RsParams), P(RsBatch), P(RsPolicy), i32, i64, _VP, _VP, _VP,
-                          _VP, _VP]),
+                          _VP, _VP, _VP]),
         "rs_plan_create": (i32, [_VP, i32, _VP, P(RsSchedule), P(_VP)]),
         "rs_plan_destroy": (i32, [_VP]),
         "rs_plan_total_robots": (i64, [_VP]),
@@ -120,7 +125,7 @@ def lib():
         "rs_plan_obs_offset": (i64, [_VP, i32]),
         "env_reset_mixed": (i32, [_VP, P(RsParams), _VP, P(RsBatch), _VP, _VP]),
         "env_run": (i32, [_VP, P(RsParams), _VP, P(RsBatch), i32, _VP, i64, _VP, _VP, _VP, _VP,
-                          _VP, _VP]),
+                          _VP, _VP, _VP]),
         "rs_autotune": (i32, [_VP, P(RsParams), _VP, i32, i32, i32, dbl, P(RsSchedule)]),
         "rs_get_schedule": (i32, [_VP, P(RsSchedule)]),
         "rs_server_create": (i32, [_VP, P(RsParams), i64, i32, P(_VP)]),
@@ -183,6 +188,14 @@ class Context:
         self.handle = _VP()
         _check(lib().rs_create(device, ctypes.byref(self.handle)))
 
+    def qp_failures(self, reset: bool = False):
+        """(infeasible, capped) certificate solves counted on the device by
+        every call on this context (waits for the device)."""
+        inf, cap = ctypes.c_int64(0), ctypes.c_int64(0)
+        _check(lib().rs_qp_failures(self.handle, ctypes.byref(inf), ctypes.byref(cap),
+                                    1 if reset else 0))
+        return int(inf.value), int(cap.value)
+
     def close(self):
         if self.handle:
             lib().rs_destroy(self.handle)
@@ -236,20 +249,21 @@ def env_reset(ctx: Context, p: RsParams, b: Batch, mask=None, obs=None, stream=N
 
 
 def env_step(ctx: Context, p: RsParams, b: Batch, actions=None, t_global: int = 0, obs=None,
-             reward=None, done=None, max_violation=None, infeasible=None, stream=None):
+             reward=None, done=None, max_violation=None, infeasible=None, qp_stats=None,
+             stream=None):
     cb = b.c()
     _check(lib().env_step(ctx.handle, ctypes.byref(p), ctypes.byref(cb), _ptr(actions), t_global,
                           _ptr(obs), _ptr(reward), _ptr(done), _ptr(max_violation),
-                          _ptr(infeasible), _stream(stream)))
+                          _ptr(infeasible), _ptr(qp_stats), _stream(stream)))
 
 
 def barrier_certificate(ctx: Context, p: RsParams, num_envs: int, robots: int, px, py, ux_nom,
                         uy_nom, ux, uy, lam=None, max_violation=None, infeasible=None,
-                        stream=None):
+                        qp_stats=None, stream=None):
     _check(lib().barrier_certificate(ctx.handle, ctypes.byref(p), num_envs, robots, _ptr(px),
                                      _ptr(py), _ptr(ux_nom), _ptr(uy_nom), _ptr(ux), _ptr(uy),
                                      _ptr(lam), _ptr(max_violation), _ptr(infeasible),
-                                     _stream(stream)))
+                                     _ptr(qp_stats), _stream(stream)))
 
 
 @dataclass
@@ -268,12 +282,12 @@ class Policy:
 
 
 def rollout(ctx: Context, p: RsParams, b: Batch, policy: Policy, horizon: int, t_global0: int,
-            obs, actions, reward, done, stream=None):
+            obs, actions, reward, done, qp_stats=None, stream=None):
     cb = b.c()
     cp = policy.c()
     _check(lib().rollout(ctx.handle, ctypes.byref(p), ctypes.byref(cb), ctypes.byref(cp), horizon,
                          t_global0, _ptr(obs), _ptr(actions), _ptr(reward), _ptr(done),
-                         _stream(stream)))
+                         _ptr(qp_stats), _stream(stream)))
 
 
 class Plan:
@@ -345,11 +359,12 @@ def env_reset_mixed(ctx: Context, p: RsParams, plan: Plan, b: Batch, mask=None, 
 
 def env_run(ctx: Context, p: RsParams, plan: Plan, b: Batch, steps: int, t_global0: int = 0,
             t_start=None, steps_per_env=None, reward_out=None, done_out=None, reward_sum=None,
-            obs_final=None, stream=None):
+            obs_final=None, qp_stats=None, stream=None):
     cb = b.c()
     _check(lib().env_run(ctx.handle, ctypes.byref(p), plan.handle, ctypes.byref(cb), steps,
                          _ptr(t_start), t_global0, _ptr(steps_per_env), _ptr(reward_out),
-                         _ptr(done_out), _ptr(reward_sum), _ptr(obs_final), _stream(stream)))
+                         _ptr(done_out), _ptr(reward_sum), _ptr(obs_final), _ptr(qp_stats),
+                         _stream(stream)))
 
 
 def autotune(ctx: Context, p: RsParams, robots, envs: int = 4096, steps: int = 50,

@@ -113,11 +113,12 @@ def test_request_bytes(R):
 def test_null_arguments_are_rejected_without_device_work(R):
     L = R.lib()
     p = R.params()
-    st = L.env_step(None, ctypes.byref(p), None, None, 0, None, None, None, None, None, None)
+    st = L.env_step(None, ctypes.byref(p), None, None, 0, None, None, None, None, None, None,
+                    None)
     assert st == 1
     assert b"NULL" in L.rs_last_error()
     st = L.barrier_certificate(None, ctypes.byref(p), 4, 4, None, None, None, None, None, None,
-                               None, None, None, None)
+                               None, None, None, None, None)
     assert st == 1
     out = ctypes.c_void_p()
     st = L.rs_plan_create(None, 4, None, None, ctypes.byref(out))
@@ -177,3 +178,23 @@ def test_params_check_covers_controllers_and_noise(R):
     assert ok(pos_gain=-1.0) == 1
     assert ok(dt=0.0) == 1
     assert ok() == 0 and L.rs_last_error() == b""
+
+
+def test_binding_argument_counts_match_the_header(R):
+    """Every function the ctypes binding declares takes as many arguments as
+    its prototype in include/robostep.h (a missing argument would shift every
+    later pointer)."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    protos = {}
+    for m in re.finditer(r"([A-Za-z_][A-Za-z0-9_]*)\s*\(([^;{]*?)\)\s*;", text, flags=re.S):
+        args = m.group(2).strip()
+        protos[m.group(1)] = 0 if args in ("", "void") else args.count(",") + 1
+    L = R.lib()
+    checked = 0
+    for name, n in protos.items():
+        fn = getattr(L, name, None)
+        if fn is None or fn.argtypes is None:
+            continue
+        assert len(fn.argtypes) == n, f"{name}: binding {len(fn.argtypes)} args, header {n}"
+        checked += 1
+    assert checked >= 25

@@ -161,3 +161,55 @@ def test_autotune_returns_valid_schedule():
         assert g >= n and g in (4, 8, 16)
         assert s.qp_iters[n] in (2 * n + 4, 4 * n + 8, 8 * n + 32)
     assert s.block_threads in (64, 128, 256)
+
+
+def test_autotuned_schedule_matches_oracle(orc):
+    """The schedule the autotuner picks (its candidates are rejected when a
+    certificate reaches the iteration cap) steps stressed mixed batches like
+    the oracle: one env_run step at a time, teacher-forced, commands exact to
+    the tolerances of the env_step tests, no capped solve."""
+    import torch
+
+    R, ctx = ctx_and_lib()
+    sizes = [4, 8, 12]
+    banner("autotune vs oracle")
+    s = R.autotune(ctx, R.params(), sizes, envs=256, steps=20, tol=1e-4)
+    counts = np.array([sizes[k % 3] for k in range(150)], np.int32)
+    plan = R.Plan(ctx, counts, s)
+    E = len(counts)
+    off = _offsets(counts)
+    b = R.Batch.empty(E, 0, env_id_base=0, total_robots=plan.total_robots)
+    b.robots = 0
+    fields = {k: np.zeros(plan.total_robots) for k in ("x", "y", "th", "gx", "gy")}
+    for e, n in enumerate(counts):
+        kind = "cluster" if e % 2 else "mixed"
+        st = synth.stressed_states(500 + e, 1, int(n), kind)
+        for k in fields:
+            fields[k][off[e]:off[e + 1]] = st[k][0]
+    for k, a in (("x", "x"), ("y", "y"), ("th", "theta"), ("gx", "goal_x"), ("gy", "goal_y")):
+        getattr(b, a).copy_(torch.from_numpy(fields[k].astype(np.float32)).cuda())
+    po = orc.Params(seed=4)
+    p = R.params(seed=4)
+    qs = torch.zeros((E, R.QPS_COUNT), dtype=torch.int32, device="cuda")
+    ctx.qp_failures(reset=True)
+    for t in range(6):
+        before = {k: host(getattr(b, a)).astype(np.float64) for k, a in
+                  (("x", "x"), ("y", "y"), ("th", "theta"), ("gx", "goal_x"), ("gy", "goal_y"))}
+        st0, ep0 = host(b.step).copy(), host(b.episode).copy()
+        R.env_run(ctx, p, plan, b, 1, t_global0=t, qp_stats=qs)
+        torch.cuda.synchronize()
+        gx_, gy_, gth = host(b.x), host(b.y), host(b.theta)
+        for e, n in enumerate(counts):
+            sl = slice(off[e], off[e + 1])
+            one = {k: v[sl].copy() for k, v in before.items()}
+            one["step"], one["episode"] = int(st0[e]), int(ep0[e])
+            out = orc.env_step(po, one, e, t)
+            assert out["status"] != 2
+            assert np.abs(one["x"] - gx_[sl]).max() <= 1e-5
+            assert np.abs(one["y"] - gy_[sl]).max() <= 1e-5
+            assert angle_diff(one["th"], gth[sl]).max() <= 6.6e-5
+    q = host(qs)
+    assert q[:, R.QPS_CAPPED].sum() == 0 and ctx.qp_failures()[1] == 0
+    assert q[:, R.QPS_ACTIVE_SET:R.QPS_GENERAL + 1].sum() > 0
+    print("tuned schedule:", {n: (s.lanes_per_env[n], s.qp_iters[n]) for n in sizes},
+          "block", s.block_threads, "stages", q[:, :R.QPS_ITERATIONS].sum(axis=0).tolist())

@@ -6,11 +6,14 @@ For every step t the oracle (1) evaluates the policy on the GPU's obs_t
 uniform, and (2) steps the state reconstructed from obs_t with the GPU's
 action; the result must reproduce obs_{t+1}, reward_t and done_t.
 
-Decisions taken in floating point: an action may differ only where the
-oracle's uniform lies within 2e-3 of a CDF boundary (the FP32 accumulation on
-the GPU can round a hidden activation to the neighbouring bfloat16, which
-moves a logit by ~1e-3); such cases must stay below 0.5% of the draws. Done
-flags follow the 1e-5 m band of the env_step tests.
+Decisions taken in floating point: a sampled action may differ from the
+oracle's only when tests/policy_flip.py explains it, i.e. when a hidden unit
+whose exact pre-activation lies within the FP32 summation error of a bf16
+rounding midpoint, rounded the other way, makes the oracle draw the GPU's
+action from the same uniform, or when the uniform lies within 1e-5 of the
+boundary between the two actions; every other mismatch fails. Explained cases
+are counted by cause and must stay below 0.5% of the draws. Done flags follow
+the 1e-5 m band of the env_step tests.
 """
 import math
 
@@ -20,6 +23,7 @@ import pytest
 from paper_2505_06771_amd import synth
 from tests.gpu_util import angle_diff, banner, batch_from_states, ctx_and_lib, dev, host, \
     prey_band, tag_band
+from tests.policy_flip import explain
 
 pytestmark = pytest.mark.gpu
 
@@ -37,12 +41,6 @@ def _state_from_obs(ob, n):
     gx, gy = x + ob[..., 2 * n + 2], y + ob[..., 2 * n + 3]
     return {k: np.ascontiguousarray(v.reshape(-1), np.float64)
             for k, v in (("x", x), ("y", y), ("th", th), ("gx", gx), ("gy", gy))}
-
-
-def _cdf_margin(logits, u):
-    pr = np.exp(logits - logits.max())
-    pr /= pr.sum()
-    return np.abs(np.cumsum(pr)[:4] - u).min()
 
 
 def run_and_check(orc, n, E, H, seed, sample_envs=None, sample_steps=None, step0=None,
@@ -88,6 +86,7 @@ def run_and_check(orc, n, E, H, seed, sample_envs=None, sample_steps=None, step0
         stepc[t + 1] = np.where(dn[t] == 1, 0, stepc[t] + 1)
         epc[t + 1] = epc[t] + dn[t]
     nact, nband, worst = 0, 0, 0.0
+    causes = {}
     pp = po.scenario == 1
     npp_band = 0
     for t in steps:
@@ -99,8 +98,11 @@ def run_and_check(orc, n, E, H, seed, sample_envs=None, sample_steps=None, step0
                 nact += 1
                 if a != ac[t, e, i]:
                     u = (bits >> 8) * 2.0 ** -24
-                    m = _cdf_margin(lg, u)
-                    assert m < 2e-3, f"t={t} e={e} i={i}: action {ac[t, e, i]} vs {a}, margin {m}"
+                    why = explain(wd, ob[t, e, i], u, int(ac[t, e, i]))
+                    assert why not in (None, "agree"), \
+                        f"t={t} e={e} i={i}: action {ac[t, e, i]} vs oracle {a} unexplained"
+                    key = why.split(":")[0]
+                    causes[key] = causes.get(key, 0) + 1
                     nband += 1
         if t + 1 >= H:
             continue
@@ -148,8 +150,8 @@ def run_and_check(orc, n, E, H, seed, sample_envs=None, sample_steps=None, step0
             assert d <= 1e-5, f"t={t} e={e}: pose gap {d}"
             assert abs(out["reward"] - rw[t, e]) <= n * 1e-5
             np.testing.assert_allclose(out["obs"], nxt, atol=1e-5, rtol=0)
-    print(f"rollout n={n}: actions {nact}, band mismatches {nband}, worst pose gap {worst:.3g}"
-          f", prey/tag band cases {npp_band}")
+    print(f"rollout n={n}: actions {nact}, explained action mismatches {nband} {causes}, "
+          f"worst pose gap {worst:.3g}, prey/tag band cases {npp_band}")
     assert nband <= max(2, 0.005 * nact)
     assert npp_band <= max(2, 0.005 * nact / n)
     return b, ob, ac, rw, dn

@@ -197,6 +197,28 @@ def test_env_step_teacher_forced_f32(orc, n):
     assert s["resets"] >= E // 2
 
 
+@pytest.mark.parametrize("n", [2, 4, 9, 16])
+def test_env_step_teacher_forced_f64(orc, n):
+    """The FP64 kernels of every lane-group width (G = 2, 4, 16; N = 9 runs
+    the 16-lane group with idle lanes) against the oracle at 1e-9."""
+    import torch
+
+    R, ctx = ctx_and_lib()
+    E = 61
+    st = _mixed_states(700 + n, E, n)
+    rng = np.random.default_rng(70 + n)
+    step0 = rng.integers(485, 500, E).astype(np.int32)
+    b = batch_from_states(R, st, n, torch.float64, env_id_base=3000, step=step0,
+                          episode=rng.integers(0, 3, E).astype(np.int32))
+    p = R.params(seed=17, dtype=R.RS_F64)
+    po = orc.Params(seed=17)
+    banner(f"env_step f64 n={n}")
+    s = _step_compare(orc, po, R, ctx, p, b, n, steps=20, t0=30,
+                      tol={"xy": 1e-9, "th": 1e-9, "obs": 1e-9})
+    print(s)
+    assert s["resets"] >= E // 2
+
+
 @pytest.mark.parametrize("kind,n,controller", [("f32", 3, 2), ("f32", 8, 2), ("f32", 6, 0),
                                                ("f64", 5, 2)])
 def test_env_step_waypoint_and_action_noise(orc, kind, n, controller):
