@@ -273,6 +273,16 @@ rs_status rollout(rs_ctx *ctx, const rs_params *p, const rs_batch *b, const rs_p
                   int32_t horizon, int64_t t_global0, float *obs, uint8_t *actions,
                   float *reward, uint8_t *done, int32_t *qp_stats, void *stream);
 
+/* Diagnostic builds only (library compiled with RS_PHASE_TIMERS, see
+ * paper_2505_06771_amd/build.py --phase-timers): copies the phase cycles of
+ * the last rollout launch's first `waves` wavefronts (wavefront w owns envs
+ * w*64/G .. w*64/G + 64/G - 1, G = lanes per env) to host out [waves][8]:
+ * shader-clock cycles spent in the observation, MLP, sampling, pre-QP, QP
+ * and post-QP phases of all steps, the number of steps in which some env of
+ * the wavefront ran the active-set loop, and the cycles of the whole step
+ * loop. Waits for the device. RS_ERR_UNSUPPORTED in the plain library. */
+rs_status rs_phase_cycles(rs_ctx *ctx, int64_t *out, int32_t waves);
+
 /* ---------------------------------------------------------------------------
  * Snapshot / restore (checkpoint and resume) of a batch's state: pose, goal,
  * step and episode arrays. The stream is counter based (env id, stream time),

@@ -3,7 +3,12 @@
 Each translation unit is compiled to an object in parallel, then the objects
 are linked into the shared library.
 
-    python -m paper_2505_06771_amd.build
+    python -m paper_2505_06771_amd.build                  # librobostep.so
+    python -m paper_2505_06771_amd.build --phase-timers   # librobostep_timers.so
+
+The second form defines RS_PHASE_TIMERS: a diagnostic library whose fused
+rollout records per-wavefront phase cycles (rs_phase_cycles); the product
+library never carries that code.
 """
 from __future__ import annotations
 
@@ -16,6 +21,7 @@ from concurrent.futures import ThreadPoolExecutor
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "librobostep.so")
+LIB_TIMERS = os.path.join(PKG, "librobostep_timers.so")
 OBJ_DIR = os.path.join(PKG, "_build")
 
 HIPCC_FLAGS = [
@@ -38,14 +44,17 @@ def _run(cmd):
     return res.returncode, err
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, phase_timers: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    os.makedirs(OBJ_DIR, exist_ok=True)
+    obj_dir = OBJ_DIR + ("_timers" if phase_timers else "")
+    lib = LIB_TIMERS if phase_timers else LIB
+    os.makedirs(obj_dir, exist_ok=True)
     inc = ["-I", os.path.join(ROOT, "include")]
+    defs = ["-DRS_PHASE_TIMERS"] if phase_timers else []
     jobs = []
     for src in sources():
-        obj = os.path.join(OBJ_DIR, os.path.basename(src)[:-4] + ".o")
-        jobs.append((obj, [hipcc, *HIPCC_FLAGS, *inc, "-c", src, "-o", obj]))
+        obj = os.path.join(obj_dir, os.path.basename(src)[:-4] + ".o")
+        jobs.append((obj, [hipcc, *HIPCC_FLAGS, *defs, *inc, "-c", src, "-o", obj]))
     if verbose:
         for _, cmd in jobs:
             print(" ".join(cmd), flush=True)
@@ -57,16 +66,16 @@ def build(verbose: bool = False) -> str:
             raise RuntimeError(f"hipcc failed on {os.path.basename(obj)} ({rc}):\n{err}")
         if verbose and err.strip():
             print(err, file=sys.stderr)
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     link = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *[o for o, _ in jobs], "-o", tmp]
     if verbose:
         print(" ".join(link), flush=True)
     rc, err = _run(link)
     if rc != 0:
         raise RuntimeError(f"hipcc link failed ({rc}):\n{err}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, phase_timers="--phase-timers" in sys.argv[1:]))

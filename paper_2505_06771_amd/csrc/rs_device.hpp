@@ -160,16 +160,11 @@ template <int G, int K, typename T> __device__ __forceinline__ T grot(T v, int l
     return dpp<(K == 1 ? 0x39 : (K == 2 ? 0x4E : 0x93))>(v);
   } else if constexpr (G == 16) {
     return dpp<0x120 + (16 - K)>(v);
-  } else {  // G == 8: no single DPP rotates within 8 lanes; permute by LDS
-    const int addr = ((lane & ~7) | ((lane + K) & 7)) << 2;
-    if constexpr (sizeof(T) == 4) {
-      return __builtin_bit_cast(T, __builtin_amdgcn_ds_bpermute(addr, __builtin_bit_cast(int, v)));
-    } else {
-      const long long b = __builtin_bit_cast(long long, v);
-      const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)(b & 0xffffffffll));
-      const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(b >> 32));
-      return __builtin_bit_cast(T, ((long long)hi << 32) | (unsigned int)lo);
-    }
+  } else {  // G == 8: two rotations of the 16-lane row; each lane keeps the
+             // one that lands inside its own 8-lane half
+    const T a = dpp<0x120 + (16 - K)>(v);  // lane (l + K) mod 16 of the row
+    const T b = dpp<0x120 + (8 - K)>(v);   // lane (l + 8 + K) mod 16 of the row
+    return ((lane & 7) + K < 8) ? a : b;
   }
 }
 
@@ -200,6 +195,46 @@ __device__ __forceinline__ void wave_lds_fence() {
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
+
+// Phase clock of a wavefront (diagnostic builds only). Built with
+// -DRS_PHASE_TIMERS, the fused rollout reads the shader clock at the
+// boundaries of its step phases and sums the cycles of each phase per
+// wavefront (wavefront-uniform, in scalar registers); without the flag every
+// call here compiles to nothing.
+enum : int {
+  kPhObs = 0,     // observation rows: assembly, LDS staging, HBM stores
+  kPhMlp = 1,     // policy MLP on MFMA
+  kPhSample = 2,  // softmax and inverse-CDF draw
+  kPhPre = 3,     // projection points, nominal command, pre-clip, bounds
+  kPhQp = 4,      // certificate QP
+  kPhPost = 5,    // unicycle map, Euler step, reward, termination, reset
+  kPhLoop = 6,    // steps in which some env of the wavefront ran the active-set loop
+  kPhTotal = 7,   // cycles of the whole step loop
+  kPhases = 8
+};
+struct PhaseClock {
+#ifdef RS_PHASE_TIMERS
+  uint64_t last;
+  uint64_t acc[kPhases];
+  __device__ __forceinline__ void start() {
+#pragma unroll
+    for (int k = 0; k < kPhases; ++k) acc[k] = 0;
+    last = __builtin_amdgcn_s_memtime();
+  }
+  __device__ __forceinline__ void mark(int k) {
+    const uint64_t now = __builtin_amdgcn_s_memtime();
+    acc[k] += now - last;
+    last = now;
+  }
+  __device__ __forceinline__ void count(int k, bool any) { acc[k] += any ? 1u : 0u; }
+  __device__ __forceinline__ uint64_t last_or_zero() const { return last; }
+#else
+  __device__ __forceinline__ uint64_t last_or_zero() const { return 0; }
+  __device__ __forceinline__ void start() {}
+  __device__ __forceinline__ void mark(int) {}
+  __device__ __forceinline__ void count(int, bool) {}
+#endif
+};
 
 // Compile-time loop: f(std::integral_constant<int, K>) for K in [B, E).
 template <int B, int E, typename F> __device__ __forceinline__ void static_for(F &&f) {

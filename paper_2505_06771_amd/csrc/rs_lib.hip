@@ -62,6 +62,7 @@ template <typename T> static bool aligned(const void *ptr) {
 }
 
 constexpr int kBlock = 256;
+static_assert(kQPStats == RS_QPS_COUNT, "qp_stats layout of robostep.h");
 
 // ---------------------------------------------------------------------------
 // env_step

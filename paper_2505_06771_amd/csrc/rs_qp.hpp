@@ -707,25 +707,38 @@ __device__ __noinline__ QPLoopOut<T> qp_active_set(QPScratch<T, G> *sh, int lane
       pend = true;
     }
     const bool frx = fx == 0, fry = fy == 0;
+    // slots in use by some group of the wavefront: the algebra of the slots
+    // beyond them (zero rows, identity rows of the factor) is skipped, which
+    // leaves every group's values exactly as if it had run
+    int qw = 0;
+#pragma unroll
+    for (int k = 1; k <= kQR; ++k) qw = __ballot(q >= k) ? k : qw;
     if (!lvalid) {
       // refactor the Gram system over the current free coordinates
       bool pd = true;
 #pragma unroll
       for (int a = 0; a < kQR; ++a) {
+        if (a < qw) {
 #pragma unroll
-        for (int b = 0; b <= a; ++b) {
-          T sgm = gsum<G>((frx ? ccx[a] * ccx[b] : T(0)) + (fry ? ccy[a] * ccy[b] : T(0)));
+          for (int b = 0; b <= a; ++b) {
+            T sgm = gsum<G>((frx ? ccx[a] * ccx[b] : T(0)) + (fry ? ccy[a] * ccy[b] : T(0)));
 #pragma unroll
-          for (int k2 = 0; k2 < b; ++k2) sgm -= L[tri(a, k2)] * L[tri(b, k2)];
-          if (b == a) {
-            sgm = a < q ? sgm : T(1);
-            pd = pd && (sgm > T(0));
-            const T rs = rsqrt_t(tmax(sgm, T(1e-30)));
-            L[tri(a, a)] = sgm * rs;
-            Linv[a] = rs;
-          } else {
-            L[tri(a, b)] = sgm * Linv[b];
+            for (int k2 = 0; k2 < b; ++k2) sgm -= L[tri(a, k2)] * L[tri(b, k2)];
+            if (b == a) {
+              sgm = a < q ? sgm : T(1);
+              pd = pd && (sgm > T(0));
+              const T rs = rsqrt_t(tmax(sgm, T(1e-30)));
+              L[tri(a, a)] = sgm * rs;
+              Linv[a] = rs;
+            } else {
+              L[tri(a, b)] = sgm * Linv[b];
+            }
           }
+        } else {
+#pragma unroll
+          for (int b = 0; b < a; ++b) L[tri(a, b)] = T(0);
+          L[tri(a, a)] = T(1);
+          Linv[a] = T(1);
         }
       }
       if (!pd) { restart = true; break; }
@@ -735,10 +748,14 @@ __device__ __noinline__ QPLoopOut<T> qp_active_set(QPScratch<T, G> *sh, int lane
     T w[kQR], rv[kQR];
 #pragma unroll
     for (int a = 0; a < kQR; ++a) {
-      T g = gsum<G>((frx ? ccx[a] * cpx : T(0)) + (fry ? ccy[a] * cpy : T(0)));
+      if (a < qw) {
+        T g = gsum<G>((frx ? ccx[a] * cpx : T(0)) + (fry ? ccy[a] * cpy : T(0)));
 #pragma unroll
-      for (int k2 = 0; k2 < a; ++k2) g -= L[tri(a, k2)] * w[k2];
-      w[a] = g * Linv[a];
+        for (int k2 = 0; k2 < a; ++k2) g -= L[tri(a, k2)] * w[k2];
+        w[a] = g * Linv[a];
+      } else {
+        w[a] = T(0);
+      }
     }
 #pragma unroll
     for (int a = kQR - 1; a >= 0; --a) {
@@ -974,11 +991,12 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
   // starts from u0.
   bool run_gi = !dead;
   if (!dead) {
-    T best = C.tol_add, bdx = T(0), bdy = T(0), bbb = T(0);
+    const T thr = C.tol_add;
+    T best = thr, bdx = T(0), bdy = T(0), bbb = T(0);
     int bid = -1, nviol = 0;
     static_for<1, KH + 1>([&](auto kc) {
       constexpr int K = decltype(kc)::value;
-      nviol += snk[K - 1] > C.tol_add ? 1 : 0;
+      nviol += snk[K - 1] > thr ? 1 : 0;
       if (snk[K - 1] > best) {
         best = snk[K - 1];
         bid = cpid[K - 1];
@@ -1007,7 +1025,7 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
       run_gi = false;  // u0 is the solution
     } else if (nv <= 2) {
       // the other violated row, if any
-      T b2 = C.tol_add, e2x = T(0), e2y = T(0), beta2 = T(0);
+      T b2 = thr, e2x = T(0), e2y = T(0), beta2 = T(0);
       int id2 = -1;
       if (nv == 2) {
         static_for<1, KH + 1>([&](auto kc) {
@@ -1048,6 +1066,23 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
         const int ra = r2 ? qa : pa, rb = r2 ? qb : pb;
         const T dx = r2 ? e2x : bdx, dy = r2 ? e2y : bdy;
         const T beta = r2 ? beta2 : bbb;
+        // projection onto the row's hyperplane with every coordinate free: the
+        // row's solution whenever it lands inside the box of both its robots
+        // (each group takes it then, whatever the other groups need)
+        const T cix = i == ra ? T(-2) * dx : (i == rb ? T(2) * dx : T(0));
+        const T ciy = i == ra ? T(-2) * dy : (i == rb ? T(2) * dy : T(0));
+        const T lamf = (gsum<G>(cix * uhx + ciy * uhy) - beta) * qdiv(T(1), T(8) * (dx * dx + dy * dy));
+        const T fvx = uhx - lamf * cix, fvy = uhy - lamf * ciy;
+        const bool end_ab = use && (i == ra || i == rb);
+        const bool fbad = end_ab && (fvx < lox || fvx > hix || fvy < loy || fvy > hiy);
+        const bool free_ok = use && lamf > T(0) && !group_any<G>(fbad, lane);
+        if (__ballot(use && !free_ok) == 0) {  // every row of the wave: the free solution
+          nux = end_ab ? fvx : nux;
+          nuy = end_ab ? fvy : nuy;
+          lam2 = r2 ? lamf : lam2;
+          lam1 = r2 ? lam1 : lamf;
+          continue;
+        }
         const int la = gbase + ra, lb = gbase + rb;
         const T cc[4] = {T(-2) * dx, T(-2) * dy, T(2) * dx, T(2) * dy};
         const T un[4] = {__shfl(uhx, la, 64), __shfl(uhy, la, 64), __shfl(uhx, lb, 64),
@@ -1110,15 +1145,15 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
           plo = bl > llo ? bv : plo;
           llo = bl > llo ? bl : llo;
         }
-        ok = ok && (!use || lhi < BIG);
-        const T lam = llo + plo * (tmin(lhi, BIG) - llo) * qdiv(T(1), plo - phh);
+        ok = ok && (!use || free_ok || lhi < BIG);
+        const T lam = free_ok ? lamf : llo + plo * (tmin(lhi, BIG) - llo) * qdiv(T(1), plo - phh);
         const bool ma = use && i == ra, mb = use && i == rb;
         const T ax = tclamp(un[0] - lam * cc[0], lo[0], hi[0]);
         const T ay = tclamp(un[1] - lam * cc[1], lo[1], hi[1]);
         const T bx = tclamp(un[2] - lam * cc[2], lo[2], hi[2]);
         const T by = tclamp(un[3] - lam * cc[3], lo[3], hi[3]);
-        nux = ma ? ax : (mb ? bx : nux);
-        nuy = ma ? ay : (mb ? by : nuy);
+        nux = free_ok ? (end_ab ? fvx : nux) : (ma ? ax : (mb ? bx : nux));
+        nuy = free_ok ? (end_ab ? fvy : nuy) : (ma ? ay : (mb ? by : nuy));
         lam2 = r2 ? lam : lam2;
         lam1 = r2 ? lam1 : lam;
       }

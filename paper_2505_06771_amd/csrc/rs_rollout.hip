@@ -36,6 +36,14 @@ typedef short shortx2 __attribute__((ext_vector_type(2)));
 constexpr int kRollBlock = 256;
 constexpr int kRollWaves = kRollBlock / 64;
 
+#ifdef RS_PHASE_TIMERS
+// Per-wavefront phase cycles of the last rollout launch (diagnostic builds):
+// [wavefront][kPhases], wavefront = block * 4 + wave; launches with more
+// wavefronts record the first kTimedWaves.
+constexpr int kTimedWaves = 1 << 16;
+__device__ unsigned long long rs_phase_cycles_dev[kTimedWaves][kPhases];
+#endif
+
 struct RolloutArgs {
   SimConst<float> C;
   int E, N, D, H;
@@ -183,22 +191,34 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
   const int row = grp * N + i;              // packed LDS row of my robot
 
   uint4 qblk = make_uint4(0u, 0u, 0u, 0u);  // this lane's Philox block (G >= 4)
+  PhaseClock pc;
+  pc.start();
+  const uint64_t t_begin = pc.last_or_zero();
   for (int t = 0; t < A.H; ++t) {
     // ---- 1. observation -> LDS (packed) -> HBM --------------------------
     if constexpr (NC > 0 && ((2 * NC + 4) & 3) == 0) {
-      // Row assembled in registers: slot s of the neighbour block holds robot
-      // j = s + (s >= i), fetched by LDS permute. The row goes to the MLP's
-      // LDS staging and to HBM as 16-byte stores.
+      // Row assembled in registers: every lane of the group posts its (x, y)
+      // to the group's LDS scratch (free between two certificate solves) and
+      // reads back all NC positions with broadcast reads; slot s of the
+      // neighbour block then holds robot j = s + (s >= i). The row goes to
+      // the MLP's LDS staging and to HBM as 16-byte stores.
       constexpr int DC = 2 * NC + 4;
+      static_assert(NC % 2 == 0 && sizeof(QPScratch<float, G>) >= NC * sizeof(float2), "");
       float rw[DC];
       rw[0] = x; rw[1] = y; rw[2] = c; rw[3] = s;
-      const int gl4 = (lane & ~(G - 1)) << 2;
-      static_for<0, NC - 1>([&](auto sc) {
-        constexpr int S = decltype(sc)::value;
-        const int src = gl4 + ((S + (S >= i ? 1 : 0)) << 2);
-        rw[4 + 2 * S] = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(src, __builtin_bit_cast(int, x))) - x;
-        rw[5 + 2 * S] = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(src, __builtin_bit_cast(int, y))) - y;
-      });
+      reinterpret_cast<float2 *>(sh)[i] = make_float2(x, y);
+      wave_lds_sync();
+      float px_[NC], py_[NC];
+#pragma unroll
+      for (int q = 0; q < NC / 2; ++q) {
+        const float4 v = reinterpret_cast<const float4 *>(sh)[q];
+        px_[2 * q] = v.x; py_[2 * q] = v.y; px_[2 * q + 1] = v.z; py_[2 * q + 1] = v.w;
+      }
+#pragma unroll
+      for (int S = 0; S < NC - 1; ++S) {
+        rw[4 + 2 * S] = (S < i ? px_[S] : px_[S + 1]) - x;
+        rw[5 + 2 * S] = (S < i ? py_[S] : py_[S + 1]) - y;
+      }
       rw[DC - 2] = gx - x;
       rw[DC - 1] = gy - y;
       if (on) {
@@ -210,8 +230,9 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
           float4 *g4 = reinterpret_cast<float4 *>(A.obs + ((size_t)t * A.E + e0) * (size_t)(NC * DC)) +
                        row * (DC / 4);
 #pragma unroll
-          for (int q = 0; q < DC / 4; ++q)
+          for (int q = 0; q < DC / 4; ++q) {
             g4[q] = make_float4(rw[4 * q], rw[4 * q + 1], rw[4 * q + 2], rw[4 * q + 3]);
+          }
         }
       }
       wave_lds_sync();
@@ -242,6 +263,7 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
       }
     }
 
+    pc.mark(kPhObs);
     // ---- 2. policy MLP on MFMA, one tile of 16 robots at a time ----------
     // hidden biases (accumulator seeds): read once per step, shared by the
     // four tiles
@@ -302,6 +324,7 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
     }
     wave_lds_sync();
 
+    pc.mark(kPhMlp);
     // ---- 3. categorical draw in the robot's own lane ----------------------
     const float4 la = logit_w[lane], lb = logit_w[64 + lane];
     const float l5[5] = {la.x, la.y, la.z, la.w, lb.x};
@@ -354,11 +377,18 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
     uint8_t *act_t = A.actions + (size_t)t * (size_t)A.E * (size_t)N;
     if (on) act_t[r] = (uint8_t)action;
 
+    pc.mark(kPhSample);
     // ---- 4. env step --------------------------------------------------------
     if (env_ok) {
       const StepOut<float> so = env_step_group<float, G, PP>(K, A.C.qp_cap, sh, lane, i, N, on, env_id,
                                                          A.t0 + (uint32_t)t, action, x, y, th, c, s, gx, gy, step,
-                                                         episode, false);
+                                                         episode, false,
+#ifdef RS_PHASE_TIMERS
+                                                         &pc
+#else
+                                                         nullptr
+#endif
+                                                         );
       if (i == 0) {
         (A.reward + (size_t)t * A.E)[(uint32_t)e] = so.reward;
         (A.done + (size_t)t * A.E)[(uint32_t)e] = so.done ? 1 : 0;
@@ -369,6 +399,18 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
   }
   if (on) { A.x[r] = x; A.y[r] = y; A.th[r] = th; A.gx[r] = gx; A.gy[r] = gy; }
   if (env_ok && i == 0) { A.step[e] = step; A.episode[e] = episode; }
+#ifdef RS_PHASE_TIMERS
+  pc.acc[kPhTotal] = pc.last - t_begin;
+  const int wid = blockIdx.x * kRollWaves + wave;
+  if (lane < kPhases && wid < kTimedWaves) {
+    unsigned long long v = 0;
+#pragma unroll
+    for (int k = 0; k < kPhases; ++k) v = lane == k ? pc.acc[k] : v;
+    rs_phase_cycles_dev[wid][lane] = v;
+  }
+#else
+  (void)t_begin;
+#endif
 }
 
 // Kernel for N robots: a compile-time robot count for N = 8 (8 lanes, no
@@ -499,4 +541,20 @@ extern "C" rs_status rollout(rs_ctx *ctx, const rs_params *p, const rs_batch *b,
   }
   RS_CHECK_HIP(hipGraphLaunch(it->second.exec, st));
   return RS_OK;
+}
+
+extern "C" rs_status rs_phase_cycles(rs_ctx *ctx, int64_t *out, int32_t waves) {
+  RS_CHECK_ARG(ctx != nullptr && out != nullptr && waves >= 1, "ctx/out/waves invalid");
+#ifdef RS_PHASE_TIMERS
+  RS_CHECK_ARG(waves <= kTimedWaves, "at most %d wavefronts are recorded", kTimedWaves);
+  RS_CHECK_HIP(hipSetDevice(ctx->device));
+  RS_CHECK_HIP(hipDeviceSynchronize());
+  RS_CHECK_HIP(hipMemcpyFromSymbol(out, HIP_SYMBOL(rs_phase_cycles_dev),
+                                   (size_t)waves * kPhases * sizeof(int64_t), 0,
+                                   hipMemcpyDeviceToHost));
+  return RS_OK;
+#else
+  set_error("phase timers are compiled out (build with RS_PHASE_TIMERS)");
+  return RS_ERR_UNSUPPORTED;
+#endif
 }

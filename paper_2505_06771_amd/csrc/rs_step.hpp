@@ -290,7 +290,7 @@ template <typename T, int G, bool PP = false>
 __device__ StepOut<T> env_step_group(ConstRef<T> K, int qp_cap, QPScratch<T, G> *sh, int lane,
                                      int i, int N, bool on, uint32_t env_id, uint32_t t, int action,
                                      T &x, T &y, T &th, T &c, T &s, T &gx, T &gy, int &step,
-                                     int &episode, bool want_viol) {
+                                     int &episode, bool want_viol, PhaseClock *pc = nullptr) {
   StepOut<T> out;
   // Constants are read from the kernel arguments phase by phase (see
   // ConstRef), so that they do not hold scalar registers across the step.
@@ -340,8 +340,15 @@ __device__ StepOut<T> env_step_group(ConstRef<T> K, int qp_cap, QPScratch<T, G> 
   T lox, hix, loy, hiy;
   wall_bounds(*K.get(), px, py, lox, hix, loy, hiy);
   T ux, uy;
+  if (pc) pc->mark(kPhPre);
   out.qp = qp_solve<T, G>(sh, K, qp_cap, lane, i, N, on, px, py, unx, uny, lox, hix, loy, hiy, ux,
                           uy);
+  if (pc) {
+    pc->mark(kPhQp);
+#ifdef RS_PHASE_TIMERS
+    pc->count(kPhLoop, __ballot(out.qp.stage >= kStActiveSet) != 0);
+#endif
+  }
   out.maxviol = want_viol ? max_violation<T, G>(*K.get(), lane, i, N, on, px, py, ux, uy, lox, hix,
                                                 loy, hiy)
                           : T(0);
@@ -381,6 +388,7 @@ __device__ StepOut<T> env_step_group(ConstRef<T> K, int qp_cap, QPScratch<T, G> 
     if (on) { x = nx; y = ny; th = nth; gx = ngx; gy = ngy; }
   }
   sincos_t(th, &s, &c);
+  if (pc) pc->mark(kPhPost);
   return out;
 }
 

@@ -93,6 +93,15 @@ _lib = None
 _VP = ctypes.c_void_p
 
 
+def use_library(path: str):
+    """Load the library from `path` (e.g. the phase-timer build) instead of
+    librobostep.so; only before the first call into the library."""
+    global LIB_PATH
+    if _lib is not None and os.path.abspath(path) != os.path.abspath(LIB_PATH):
+        raise RuntimeError("the library is already loaded")
+    LIB_PATH = path
+
+
 def lib():
     """Load the HIP library; raise if it has not been built."""
     global _lib
@@ -112,6 +121,7 @@ def lib():
         "rs_destroy": (i32, [_VP]),
         "env_reset": (i32, [_VP, P(RsParams), P(RsBatch), _VP, _VP, _VP]),
         "rs_qp_failures": (i32, [_VP, P(i64), P(i64), i32]),
+        "rs_phase_cycles": (i32, [_VP, _VP, i32]),
         "env_step": (i32, [_VP, P(RsParams), P(RsBatch), _VP, i64, _VP, _VP, _VP, _VP, _VP, _VP,
                            _VP]),
         "barrier_certificate": (i32, [_VP, P(RsParams), i32, i32, _VP, _VP, _VP, _VP, _VP, _VP,
@@ -187,6 +197,15 @@ class Context:
     def __init__(self, device: int = 0):
         self.handle = _VP()
         _check(lib().rs_create(device, ctypes.byref(self.handle)))
+
+    def phase_cycles(self, waves: int):
+        """[waves, 8] phase cycles of the last rollout launch (diagnostic
+        library only, see build.py --phase-timers)."""
+        import numpy as np
+
+        out = np.zeros((waves, 8), np.int64)
+        _check(lib().rs_phase_cycles(self.handle, out.ctypes.data, waves))
+        return out
 
     def qp_failures(self, reset: bool = False):
         """(infeasible, capped) certificate solves counted on the device by
