@@ -54,7 +54,7 @@ typedef enum {
 } rs_status;
 
 enum { RS_F32 = 0, RS_F64 = 1 };
-enum { RS_CTRL_DISCRETE = 0, RS_CTRL_GOTO = 1, RS_CTRL_WAYPOINT = 2 };
+enum { RS_CTRL_DISCRETE = 0, RS_CTRL_GOTO = 1, RS_CTRL_WAYPOINT = 2, RS_CTRL_POSE = 3 };
 enum { RS_SCN_NAVIGATION = 0, RS_SCN_PREDATOR_PREY = 1 };
 enum { RS_MAX_ROBOTS = 16 };
 
@@ -65,7 +65,8 @@ enum { RS_MAX_ROBOTS = 16 };
  * speed 0.2, go-to-goal gain 1, wheel radius 0.016 and axle 0.105 (wheel
  * speed limit v_max / R), goal radius 0.05, 500-step episodes, reset lattice
  * 1e-4 m inside a 0.2 m margin with 0.3 m separation; waypoints 0.2 ahead,
- * position controller gains k_v 0.8 and k_w pi/2; no action noise;
+ * position controller gains k_v 0.8 and k_w pi/2; pose controller gains
+ * k_rho 0.8, k_alpha 2, k_beta 0.5; no action noise;
  * Navigation scenario (Predator-Prey: prey 0.3 m/s, tag radius 0.25, tag
  * reward 10). */
 typedef struct {
@@ -85,7 +86,7 @@ typedef struct {
   double min_sep;
   double grid;
   int32_t max_steps;   /* <= 0 disables the time limit */
-  int32_t controller;  /* RS_CTRL_DISCRETE, RS_CTRL_GOTO or RS_CTRL_WAYPOINT */
+  int32_t controller;  /* RS_CTRL_DISCRETE, RS_CTRL_GOTO, RS_CTRL_WAYPOINT or RS_CTRL_POSE */
   int32_t dtype;       /* RS_F32 or RS_F64 */
   int32_t qp_max_iters; /* cap on active-set iterations per env; 0 = 8N+32 */
   uint64_t seed;       /* key of the counter-based stream */
@@ -97,6 +98,9 @@ typedef struct {
   double tag_radius;   /* RS_SCN_PREDATOR_PREY: tag when a centre is closer than this */
   double tag_reward;   /* RS_SCN_PREDATOR_PREY: team reward of a step with a tag */
   int32_t scenario;    /* RS_SCN_NAVIGATION or RS_SCN_PREDATOR_PREY */
+  double pose_gain_rho;   /* RS_CTRL_POSE: k_rho (linear speed per metre to go) */
+  double pose_gain_alpha; /* RS_CTRL_POSE: k_alpha (turn rate per radian of bearing) */
+  double pose_gain_beta;  /* RS_CTRL_POSE: k_beta (weight of the goal-heading error) */
 } rs_params;
 
 /* Environment batch: device structure-of-arrays views, caller-owned. */
@@ -199,7 +203,15 @@ rs_status env_reset(rs_ctx *ctx, const rs_params *p, const rs_batch *b, const ui
  *     {0, +x, -x, +y, -y}[a_i] steered to by v = k_v rho cos(alpha),
  *     w = k_w sin(alpha) (rho = |w_i - (x_i, y_i)|, alpha = bearing of w_i
  *     from the heading; v = w = 0 at the waypoint), taken to the projection
- *     point as (v cos th - l w sin th, v sin th + l w cos th); then, when
+ *     point as (v cos th - l w sin th, v sin th + l w cos th); or for
+ *     RS_CTRL_POSE (waypoint poses followed by a unicycle pose controller:
+ *     Sec. 4.1, unicycle controllers to positions/poses; Table 1) the pose
+ *     waypoint_step ahead along dir(a) with heading along dir(a) (a = 0: the
+ *     robot's own pose) steered to by v = k_rho rho cos(alpha), w = k_alpha
+ *     alpha + k_rho (sin(alpha) cos(alpha)/alpha)(alpha + k_beta beta)
+ *     (alpha = bearing of the goal position from the heading in (-pi, pi],
+ *     beta = bearing of it from the goal heading, 0 for these waypoints),
+ *     taken to the projection point the same way; then, when
  *     action_noise = sigma > 0 (action-noise domain randomisation, Sec. 7),
  *     plus sigma (2 u - 1) per coordinate with u the 24-bit uniforms of
  *     words 0 (x) and 1 (y) of block (env_id, t_global, 6<<24 | i, 0);

@@ -50,6 +50,8 @@ class OrcParams(ctypes.Structure):
         ("ang_gain", ctypes.c_double), ("action_noise", ctypes.c_double),
         ("prey_speed", ctypes.c_double), ("tag_radius", ctypes.c_double),
         ("tag_reward", ctypes.c_double), ("scenario", ctypes.c_int32),
+        ("pose_gain_rho", ctypes.c_double), ("pose_gain_alpha", ctypes.c_double),
+        ("pose_gain_beta", ctypes.c_double),
     ]
 
 
@@ -86,6 +88,9 @@ class Params:
     tag_radius: float = 0.25
     tag_reward: float = 10.0
     scenario: int = 0
+    pose_gain_rho: float = 0.8
+    pose_gain_alpha: float = 2.0
+    pose_gain_beta: float = 0.5
 
     def c(self) -> OrcParams:
         return OrcParams(**{f.name: getattr(self, f.name) for f in fields(self)})
@@ -124,6 +129,7 @@ def lib():
         L.orc_si_to_uni.argtypes = [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                     _D, _D]
         L.orc_unicycle_position.argtypes = [_P] + [ctypes.c_double] * 5 + [_D, _D]
+        L.orc_unicycle_pose.argtypes = [_P] + [ctypes.c_double] * 6 + [_D, _D]
         L.orc_uni_to_si.argtypes = [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double, _D,
                                     _D]
         L.orc_action_noise.argtypes = [_P, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32, _D,
@@ -249,6 +255,15 @@ def unicycle_position(p: Params, x: float, y: float, theta: float, wx: float, wy
     cp = p.c()
     lib().orc_unicycle_position(ctypes.byref(cp), x, y, theta, wx, wy, ctypes.byref(v),
                                 ctypes.byref(w))
+    return v.value, w.value
+
+
+def unicycle_pose(p: Params, x: float, y: float, theta: float, wx: float, wy: float,
+                  wth: float):
+    v, w = ctypes.c_double(), ctypes.c_double()
+    cp = p.c()
+    lib().orc_unicycle_pose(ctypes.byref(cp), x, y, theta, wx, wy, wth, ctypes.byref(v),
+                            ctypes.byref(w))
     return v.value, w.value
 
 

@@ -530,6 +530,38 @@ void orc_unicycle_position(const orc_params *p, double x, double y, double theta
   *w = p->ang_gain * sin(alpha);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Unicycle pose controller (Sec. 4.1: unicycle controllers drive robots to  */
+/* desired positions or poses; Table 1 times a pose controller beside the    */
+/* position one). The paper gives no law. Reading: the globally stabilising  */
+/* law of Aicardi, Casalino, Bicchi and Balestrino (1995) on the polar error */
+/* of the goal pose (wx, wy, wth): rho = distance to the goal position, phi  */
+/* its bearing (wth when rho = 0), alpha = wrap(phi - theta) the bearing    */
+/* relative to the heading, beta = wrap(phi - wth) the bearing relative to   */
+/* the goal heading, wrap to (-pi, pi] by atan2 of sine and cosine;          */
+/*   v = k_rho rho cos(alpha),                                               */
+/*   w = k_alpha alpha + k_rho (sin(alpha) cos(alpha) / alpha)               */
+/*       (alpha + k_beta beta),                                              */
+/* with sin(alpha)/alpha = 1 at alpha = 0. Waypoint poses of the action      */
+/* space: a move action a sets the pose waypoint_step ahead of the centre    */
+/* along dir(a), heading along dir(a) (so beta = 0 there); staying sets the */
+/* robot's own pose (v = w = 0).                                             */
+/* ------------------------------------------------------------------------ */
+static double wrap_angle(double a) { return atan2(sin(a), cos(a)); }
+
+void orc_unicycle_pose(const orc_params *p, double x, double y, double theta, double wx,
+                       double wy, double wth, double *v, double *w) {
+  double ex = wx - x, ey = wy - y;
+  double rho = sqrt(ex * ex + ey * ey);
+  double phi = rho > 0.0 ? atan2(ey, ex) : wth;
+  double alpha = wrap_angle(phi - theta);
+  double beta = wrap_angle(phi - wth);
+  double sinc = alpha != 0.0 ? sin(alpha) / alpha : 1.0;
+  *v = p->pose_gain_rho * rho * cos(alpha);
+  *w = p->pose_gain_alpha * alpha +
+       p->pose_gain_rho * sinc * cos(alpha) * (alpha + p->pose_gain_beta * beta);
+}
+
 /* The projection point sits l ahead of the axle: its velocity is the
  * centre's velocity v (cos th, sin th) plus l w (-sin th, cos th). */
 void orc_uni_to_si(const orc_params *p, double theta, double v, double w, double *ux,
@@ -573,6 +605,12 @@ void orc_nominal_command(const orc_params *p, int32_t n, uint64_t env_id, int64_
         double wx = x[i] + p->waypoint_step * dx, wy = y[i] + p->waypoint_step * dy;
         double v, w;
         orc_unicycle_position(p, x[i], y[i], th[i], wx, wy, &v, &w);
+        orc_uni_to_si(p, th[i], v, w, &unx[i], &uny[i]);
+      } else if (p->controller == 3) {
+        double wx = x[i] + p->waypoint_step * dx, wy = y[i] + p->waypoint_step * dy;
+        double wth = (dx != 0.0 || dy != 0.0) ? atan2(dy, dx) : th[i];
+        double v, w;
+        orc_unicycle_pose(p, x[i], y[i], th[i], wx, wy, wth, &v, &w);
         orc_uni_to_si(p, th[i], v, w, &unx[i], &uny[i]);
       } else {
         unx[i] = p->action_speed * dx;

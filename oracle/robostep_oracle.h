@@ -43,7 +43,8 @@ typedef struct {
   double grid;               /* reset sampler lattice pitch */
   int32_t max_steps;         /* <= 0 disables the time limit */
   int32_t controller;        /* 0: discrete moves, 1: proportional go-to-goal,
-                                2: waypoints followed by a unicycle position controller */
+                                2: waypoints followed by a unicycle position controller,
+                                3: waypoint poses followed by a unicycle pose controller */
   uint64_t seed;             /* Philox key */
   double waypoint_step;      /* controller 2: distance of the waypoint a move action sets */
   double pos_gain;           /* controller 2: k_v, linear speed per metre of distance */
@@ -53,6 +54,9 @@ typedef struct {
   double tag_radius;         /* scenario 1: a robot centre closer than this tags the prey */
   double tag_reward;         /* scenario 1: team reward of a step with a tag */
   int32_t scenario;          /* 0: Navigation, 1: Predator-Prey */
+  double pose_gain_rho;      /* controller 3: k_rho (linear speed per metre) */
+  double pose_gain_alpha;    /* controller 3: k_alpha (turn rate per radian of bearing) */
+  double pose_gain_beta;     /* controller 3: k_beta (weight of the goal-heading error) */
 } orc_params;
 
 /* Philox4x32-10 block cipher (Salmon, Moraes, Dror, Shaw, SC'11). */
@@ -96,6 +100,11 @@ double orc_max_violation(const orc_params *p, int32_t n, const double *px, const
  * toward the waypoint (wx, wy). */
 void orc_unicycle_position(const orc_params *p, double x, double y, double theta, double wx,
                            double wy, double *v, double *w);
+
+/* Unicycle pose controller: (v, w) that drive a robot at (x, y, theta) to
+ * the pose (wx, wy, wth). */
+void orc_unicycle_pose(const orc_params *p, double x, double y, double theta, double wx,
+                       double wy, double wth, double *v, double *w);
 
 /* Unicycle command (v, w) -> velocity of the projection point. */
 void orc_uni_to_si(const orc_params *p, double theta, double v, double w, double *ux,

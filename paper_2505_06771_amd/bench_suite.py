@@ -9,7 +9,8 @@
                    schedule) vs per-size env_step launches (5 per step)
   rollout_waypoint_noise
                    the fused 16384 x 8 x 128 policy rollout with waypoint
-                   actions (unicycle position controller) and action noise,
+                   actions (unicycle position controller) and with waypoint
+                   poses (unicycle pose controller), both with action noise,
                    beside the same rollout with discrete moves and no noise
                    (kernel ms per launch from HIP events, robot-steps/s)
   rollout_predator_prey
@@ -336,7 +337,8 @@ def rollout_waypoint_noise(R, ctx, seed=0, launches=10, E=16384, n=8, H=128, sig
     res = {"config": "rollout_waypoint_noise", "envs": E, "robots": n, "horizon": H,
            "launches": launches, "action_noise": sigma}
     for name, kw in (("discrete", {}),
-                     ("waypoint_noise", {"controller": R.RS_CTRL_WAYPOINT, "action_noise": sigma})):
+                     ("waypoint_noise", {"controller": R.RS_CTRL_WAYPOINT, "action_noise": sigma}),
+                     ("pose_noise", {"controller": R.RS_CTRL_POSE, "action_noise": sigma})):
         med, _ = _time_rollout(R, ctx, R.params(seed=seed, **kw), E, n, H, launches, seed)
         res[f"kernel_ms_median_{name}"] = med
         res[f"robot_steps_per_s_{name}"] = E * n * H / (med * 1e-3)

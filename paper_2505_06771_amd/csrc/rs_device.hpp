@@ -34,6 +34,9 @@ __device__ __forceinline__ double sqrt_t(double a) { return sqrt(a); }
 __device__ __forceinline__ float rsqrt_t(float a) { return __builtin_amdgcn_rsqf(a); }
 __device__ __forceinline__ double rsqrt_t(double a) { return rsqrt(a); }
 
+__device__ __forceinline__ float atan2_t(float y, float x) { return atan2f(y, x); }
+__device__ __forceinline__ double atan2_t(double y, double x) { return atan2(y, x); }
+
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32 multiplies
 // with a Weyl key schedule.
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
@@ -249,6 +252,7 @@ template <typename T> struct SimConst {
   T xwl, xwh, ywl, ywh;  // walls pulled in by r_s/2: x_min + r_s/2, x_max - r_s/2, ...
   T dt, l, inv_l, gamma, rs2, kb, vmax, vmax4, aspeed, kp;
   T wstep, kv, kw;  // waypoint distance and position-controller gains
+  T krho, kalpha;   // pose-controller gains (its k_beta term vanishes on move waypoints)
   T noise;          // action-noise amplitude (0: off)
   T prey_step, tag_r, tag_reward;  // Predator-Prey: prey move per step, tag radius, reward
   T R, halfL, wheel_lim;  // R <= 0: no saturation; halfL = L/2

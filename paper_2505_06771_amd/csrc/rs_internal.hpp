@@ -86,7 +86,8 @@ rs_status check_params(const rs_params *p);
 
 // Controllers whose nominal command comes from a per-robot action.
 inline bool action_driven(int controller) {
-  return controller == RS_CTRL_DISCRETE || controller == RS_CTRL_WAYPOINT;
+  return controller == RS_CTRL_DISCRETE || controller == RS_CTRL_WAYPOINT ||
+         controller == RS_CTRL_POSE;
 }
 
 template <typename T> SimConst<T> make_const(const rs_params &p) {
@@ -108,6 +109,8 @@ template <typename T> SimConst<T> make_const(const rs_params &p) {
   C.wstep = (T)p.waypoint_step;
   C.kv = (T)p.pos_gain;
   C.kw = (T)p.ang_gain;
+  C.krho = (T)p.pose_gain_rho;
+  C.kalpha = (T)p.pose_gain_alpha;
   C.noise = (T)p.action_noise;
   C.prey_step = (T)(p.prey_speed * p.dt);
   C.tag_r = (T)p.tag_radius;

@@ -36,12 +36,15 @@ rs_status check_params(const rs_params *p) {
   RS_CHECK_ARG(p->grid > 0, "grid must be > 0");
   RS_CHECK_ARG(p->dtype == RS_F32 || p->dtype == RS_F64, "dtype must be RS_F32 or RS_F64");
   RS_CHECK_ARG(p->controller == RS_CTRL_DISCRETE || p->controller == RS_CTRL_GOTO ||
-                   p->controller == RS_CTRL_WAYPOINT,
+                   p->controller == RS_CTRL_WAYPOINT || p->controller == RS_CTRL_POSE,
                "unknown controller %d", p->controller);
   RS_CHECK_ARG(p->waypoint_step >= 0 && p->pos_gain >= 0 && p->ang_gain >= 0,
                "waypoint step and controller gains must be >= 0");
-  RS_CHECK_ARG(p->controller != RS_CTRL_WAYPOINT || p->waypoint_step > 0,
-               "the waypoint controller needs waypoint_step > 0");
+  RS_CHECK_ARG((p->controller != RS_CTRL_WAYPOINT && p->controller != RS_CTRL_POSE) ||
+                   p->waypoint_step > 0,
+               "the waypoint and pose controllers need waypoint_step > 0");
+  RS_CHECK_ARG(p->pose_gain_rho >= 0 && p->pose_gain_alpha >= 0 && p->pose_gain_beta >= 0,
+               "pose controller gains must be >= 0");
   RS_CHECK_ARG(p->action_noise >= 0 && p->action_noise <= 1e3, "action_noise must be in [0, 1e3]");
   RS_CHECK_ARG(p->scenario == RS_SCN_NAVIGATION || p->scenario == RS_SCN_PREDATOR_PREY,
                "unknown scenario %d", p->scenario);
@@ -376,6 +379,9 @@ void rs_params_default(rs_params *p) {
   p->tag_radius = 0.25;
   p->tag_reward = 10.0;
   p->scenario = RS_SCN_NAVIGATION;
+  p->pose_gain_rho = 0.8;
+  p->pose_gain_alpha = 2.0;
+  p->pose_gain_beta = 0.5;
 }
 
 rs_status rs_params_check(const rs_params *p) {

@@ -315,6 +315,21 @@ __device__ StepOut<T> env_step_group(ConstRef<T> K, int qp_cap, QPScratch<T, G> 
       const T w = C.kw * (c * T(ddy) - s * T(ddx));
       unx = v * c - C.l * w * s;
       uny = v * s + C.l * w * c;
+    } else if (C.controller == 3) {
+      // Pose waypoint wstep ahead along the unit axis d, heading along d,
+      // steered to by the pose law v = k_rho rho cos(alpha), w = k_alpha
+      // alpha + k_rho (sin(alpha) cos(alpha) / alpha)(alpha + k_beta beta).
+      // The waypoint lies on the ray of its own heading, so beta = 0 and the
+      // turn rate is k_alpha alpha + k_rho sin(alpha) cos(alpha), with
+      // cos(alpha) = (c, s).d, sin(alpha) = (c, s) x d; staying (d = 0)
+      // gives v = w = 0 (alpha = 0 set explicitly: the products with d = 0
+      // can be signed zeros, and atan2(+0, -0) = pi).
+      const T ca = c * T(ddx) + s * T(ddy), sa = c * T(ddy) - s * T(ddx);
+      const T alpha = (ddx != 0 || ddy != 0) ? atan2_t(sa, ca) : T(0);
+      const T v = C.krho * C.wstep * ca;
+      const T w = C.kalpha * alpha + C.krho * sa * ca;
+      unx = v * c - C.l * w * s;
+      uny = v * s + C.l * w * c;
     } else {
       unx = C.aspeed * T(ddx);
       uny = C.aspeed * T(ddy);

@@ -16,7 +16,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "librobostep.so")
 
 RS_F32, RS_F64 = 0, 1
-RS_CTRL_DISCRETE, RS_CTRL_GOTO, RS_CTRL_WAYPOINT = 0, 1, 2
+RS_CTRL_DISCRETE, RS_CTRL_GOTO, RS_CTRL_WAYPOINT, RS_CTRL_POSE = 0, 1, 2, 3
 RS_SCN_NAVIGATION, RS_SCN_PREDATOR_PREY = 0, 1
 # certificate statistics (qp_stats slots)
 QPS_BOX, QPS_ONE_ROW, QPS_TWO_ROWS, QPS_SHARED_ROBOT, QPS_ACTIVE_SET, QPS_GENERAL = range(6)
@@ -49,6 +49,8 @@ class RsParams(ctypes.Structure):
         ("ang_gain", ctypes.c_double), ("action_noise", ctypes.c_double),
         ("prey_speed", ctypes.c_double), ("tag_radius", ctypes.c_double),
         ("tag_reward", ctypes.c_double), ("scenario", ctypes.c_int32),
+        ("pose_gain_rho", ctypes.c_double), ("pose_gain_alpha", ctypes.c_double),
+        ("pose_gain_beta", ctypes.c_double),
     ]
 
 

@@ -84,3 +84,17 @@ def tag_band(po, x, y, qx, qy, tol=1e-5):
     """True when some robot centre is within `tol` of the tag radius."""
     d = np.hypot(np.asarray(x) - qx, np.asarray(y) - qy)
     return bool((np.abs(d - po.tag_radius) < tol).any())
+
+
+def pose_band(po, th, actions, tol=1e-4):
+    """Robots whose pose-controller bearing (controller 3) lies within `tol` of
+    +-pi: the goal straight behind, where the law turns one way or the other
+    and FP32 rounding may pick either. th, actions: arrays of one shape."""
+    if getattr(po, "controller", 0) != 3:
+        return np.zeros(np.shape(th), bool)
+    a = np.asarray(actions)
+    dx = (a == 1).astype(np.float64) - (a == 2)
+    dy = (a == 3).astype(np.float64) - (a == 4)
+    c, s = np.cos(th), np.sin(th)
+    ca, sa = c * dx + s * dy, c * dy - s * dx
+    return (a != 0) & (ca < 0) & (np.abs(sa) < tol)

@@ -62,7 +62,8 @@ def test_params_struct_matches_oracle_constants(R):
               "boundary_gain_factor", "v_max", "action_speed", "kp", "wheel_radius",
               "base_length", "goal_radius", "reset_margin", "min_sep", "grid", "max_steps",
               "waypoint_step", "pos_gain", "ang_gain", "action_noise", "prey_speed",
-              "tag_radius", "tag_reward", "scenario"):
+              "tag_radius", "tag_reward", "scenario", "pose_gain_rho", "pose_gain_alpha",
+              "pose_gain_beta"):
         assert getattr(o, f) == getattr(p, f), f
 
 
@@ -72,7 +73,7 @@ def test_struct_layouts_match_the_header(R, tmp_path):
 
     src = tmp_path / "sizes.c"
     fields = {"rs_params": ["seed", "qp_max_iters", "grid", "waypoint_step", "action_noise",
-                            "tag_reward", "scenario"],
+                            "tag_reward", "scenario", "pose_gain_rho", "pose_gain_beta"],
               "rs_batch": ["env_id_base", "episode"],
               "rs_policy": ["in_dim", "b3"], "rs_schedule": ["qp_iters", "lanes_per_env"],
               "rs_request_info": ["finish_time", "horizon"],
@@ -168,7 +169,10 @@ def test_params_check_covers_controllers_and_noise(R):
     assert ok() == 0
     assert ok(controller=R.RS_CTRL_WAYPOINT, action_noise=0.05) == 0
     assert ok(controller=R.RS_CTRL_GOTO) == 0
-    assert ok(controller=3) == 1 and b"controller" in L.rs_last_error()
+    assert ok(controller=R.RS_CTRL_POSE) == 0
+    assert ok(controller=4) == 1 and b"controller" in L.rs_last_error()
+    assert ok(controller=R.RS_CTRL_POSE, waypoint_step=0.0) == 1
+    assert ok(controller=R.RS_CTRL_POSE, pose_gain_alpha=-1.0) == 1
     assert ok(controller=R.RS_CTRL_WAYPOINT, waypoint_step=0.0) == 1
     assert b"waypoint_step" in L.rs_last_error()
     assert ok(action_noise=-0.1) == 1 and b"action_noise" in L.rs_last_error()

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 from paper_2505_06771_amd import synth
-from tests.gpu_util import angle_diff, banner, ctx_and_lib, dev, host
+from tests.gpu_util import angle_diff, banner, ctx_and_lib, dev, host, pose_band
 
 pytestmark = pytest.mark.gpu
 
@@ -47,8 +47,9 @@ def test_reset_mixed_matches_oracle(orc):
         assert angle_diff(th[off[e]:off[e + 1]], oth).max() <= 1e-6
 
 
-@pytest.mark.parametrize("extra", [{}, {"controller": 2, "action_noise": 0.05}],
-                         ids=["discrete", "waypoint_noise"])
+@pytest.mark.parametrize("extra", [{}, {"controller": 2, "action_noise": 0.05},
+                                   {"controller": 3, "action_noise": 0.05}],
+                         ids=["discrete", "waypoint_noise", "pose_noise"])
 def test_env_run_one_step_teacher_forced(orc, extra):
     import torch
 
@@ -81,6 +82,9 @@ def test_env_run_one_step_teacher_forced(orc, extra):
             sl = slice(off[e], off[e + 1])
             one = {k: v[sl].copy() for k, v in before.items()}
             one["step"], one["episode"] = int(st0[e]), int(ep0[e])
+            acts = [orc.random_action(po, e, 300 + t, i) for i in range(n)]
+            if pose_band(po, one["th"], acts).any():
+                continue  # pose controller: goal bearing at +-pi
             out = orc.env_step(po, one, e, 300 + t)
             assert out["status"] != 2
             assert out["done"] == gdn[e]

@@ -22,7 +22,7 @@ import pytest
 
 from paper_2505_06771_amd import synth
 from tests.gpu_util import angle_diff, banner, batch_from_states, ctx_and_lib, dev, host, \
-    prey_band, tag_band
+    pose_band, prey_band, tag_band
 from tests.policy_flip import explain
 
 pytestmark = pytest.mark.gpu
@@ -116,6 +116,9 @@ def run_and_check(orc, n, E, H, seed, sample_envs=None, sample_steps=None, step0
             one = {kk: s[kk][k * n:(k + 1) * n].copy() for kk in ("x", "y", "th", "gx", "gy")}
             one["step"], one["episode"] = int(s["step"][k]), int(s["episode"][k])
             pre = {kk: s[kk][k * n:(k + 1) * n].copy() for kk in ("x", "y", "gx", "gy")}
+            if pose_band(po, one["th"], acts[k * n:(k + 1) * n]).any():
+                npp_band += 1  # pose controller: goal bearing at +-pi
+                continue
             out = orc.env_step(po, one, int(e), t0 + t, actions=acts[k * n:(k + 1) * n])
             assert out["status"] != 2
             if pp:
@@ -169,15 +172,16 @@ def test_rollout_predator_prey(orc, n):
     assert dn.sum() >= E // 2
 
 
-@pytest.mark.parametrize("n", [4, 8])
-def test_rollout_waypoint_and_action_noise(orc, n):
-    """Policy actions as waypoints for the unicycle position controller, with
-    uniform action noise (sigma 0.05 m/s)."""
+@pytest.mark.parametrize("n,controller", [(4, 2), (8, 2), (4, 3), (8, 3)])
+def test_rollout_waypoint_and_action_noise(orc, n, controller):
+    """Policy actions as waypoints for the unicycle position controller (2) or
+    as waypoint poses for the unicycle pose controller (3), with uniform action
+    noise (sigma 0.05 m/s)."""
     E = {4: 67, 8: 131}[n]
     rng = np.random.default_rng(50 + n)
     step0 = rng.integers(470, 500, E).astype(np.int32)
-    run_and_check(orc, n, E, H=40, seed=60 + n, step0=step0,
-                  extra=dict(controller=2, action_noise=0.05))
+    run_and_check(orc, n, E, H=40, seed=60 + n + 10 * controller, step0=step0,
+                  extra=dict(controller=controller, action_noise=0.05))
 
 
 @pytest.mark.parametrize("n", [2, 3, 4, 6, 8, 14])
