@@ -208,7 +208,7 @@ __global__ __launch_bounds__(kBlock) void k_barrier(BarrierArgs<T> A) {
       const int j = i + k >= N ? i + k - N : i + k;
       const int a = i < j ? i : j, b = i < j ? j : i;
       T val = T(0);
-      if (info.in_lds) {
+      if (act.rows_in_lds) {
         for (int s = 0; s < info.q; ++s)
           if (sh->act[s] == (a | (b << 8))) val = T(2) * sh->lam[s];
       } else {

@@ -450,6 +450,7 @@ constexpr int kQR = 4;
 
 template <typename T> struct QPActive {
   int q;
+  int rows_in_lds;  // 1: the rows are in sh->act / sh->lam (active-set loops)
   int sa[kQR], sb[kQR];
   T slam[kQR];
 };
@@ -514,12 +515,12 @@ template <int G> __device__ __forceinline__ void pair_owner_g(int a, int b, int 
   else { owner = b; k = G - d; }
 }
 
-// Result of the active-set loop (commands, status and the active rows).
+// Result of the active-set loop: six values, so that it comes back in
+// registers (a larger result would travel through scratch memory, and
+// reading it back would wait for every outstanding store of the wavefront).
 template <typename T> struct QPLoopOut {
   T ux, uy;
   int status, iters, q, in_lds;
-  int sa[kQR], sb[kQR];
-  T slam[kQR];
 };
 
 // The active-set loop, kept out of line: it runs for the few environments the
@@ -527,14 +528,16 @@ template <typename T> struct QPLoopOut {
 // step. It rebuilds the pair geometry and the box clip from the arguments and
 // starts from the box clip or, with `seed`, from the one-row solution of row
 // (fpa, fpb) with multiplier fl1 (fdx, fdy = p_a - p_b). Every lane of the
-// group calls it together. Only scalars cross the call.
+// group calls it together. Only scalars cross the call. With want_rows the
+// active rows and their multipliers are left in sh->act / sh->lam (as the
+// general solver leaves them) for the caller to read.
 template <typename T, int G>
 __device__ __noinline__ QPLoopOut<T> qp_active_set(QPScratch<T, G> *sh, int lane, int i, int N,
                                                    bool on, T px, T py, T uhx, T uhy, T lox,
                                                    T hix, T loy, T hiy, bool seed, int fpa,
                                                    int fpb, T fl1, T fdx, T fdy, T rs2, T gamma,
                                                    T vmax4, T tol_add, T eps_z, T eps_r,
-                                                   int qp_cap) {
+                                                   int qp_cap, bool want_rows) {
   constexpr int KH = G / 2;
   const T BIG = big_v<T>();
   SimConst<T> C{};
@@ -905,11 +908,17 @@ __device__ __noinline__ QPLoopOut<T> qp_active_set(QPScratch<T, G> *sh, int lane
   out.status = info.status;
   out.iters = info.iters;
   out.q = q;
+  if (want_rows && !out.in_lds) {
+    if (i == 0) {
 #pragma unroll
-  for (int a = 0; a < kQR; ++a) {
-    out.sa[a] = sa[a];
-    out.sb[a] = sb[a];
-    out.slam[a] = slam[a];
+      for (int a = 0; a < kQR; ++a) {
+        if (a < q) {
+          sh->act[a] = sa[a] | (sb[a] << 8);
+          sh->lam[a] = slam[a];
+        }
+      }
+    }
+    wave_lds_fence();
   }
   __builtin_amdgcn_s_setprio(0);
   return out;
@@ -1216,7 +1225,7 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
     const QPLoopOut<T> r = qp_active_set<T, G>(sh, lane, i, N, on, px, py, uhx, uhy, lox, hix,
                                                loy, hiy, seed, fpa, fpb, fl1, fdx, fdy, C.rs2,
                                                C.gamma, C.vmax4, C.tol_add, C.eps_z, C.eps_r,
-                                               qp_cap);
+                                               qp_cap, act_out != nullptr);
     ux = r.ux;
     uy = r.uy;
     info.status = r.status;
@@ -1226,12 +1235,7 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
     info.stage = r.in_lds ? kStGeneral : kStActiveSet;
     if (act_out) {
       act_out->q = r.q;
-#pragma unroll
-      for (int a = 0; a < kQR; ++a) {
-        act_out->sa[a] = r.sa[a];
-        act_out->sb[a] = r.sb[a];
-        act_out->slam[a] = r.slam[a];
-      }
+      act_out->rows_in_lds = 1;
     }
     return info;
   }
@@ -1247,6 +1251,7 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
   info.q = fq;
   if (act_out) {
     act_out->q = fq;
+    act_out->rows_in_lds = 0;
     act_out->sa[0] = fq > 0 ? fpa : -1;
     act_out->sb[0] = fq > 0 ? fpb : -1;
     act_out->slam[0] = fq > 0 ? fl1 : T(0);
