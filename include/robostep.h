@@ -318,7 +318,8 @@ rs_status rs_restore(rs_ctx *ctx, int32_t dtype, const rs_batch *b, int64_t robo
 /* ---------------------------------------------------------------------------
  * Mixed-size batches (environments with different robot counts in one launch).
  * A plan holds the schedule: envs grouped by robot count into wavefront tiles
- * (envs per wavefront chosen per robot count by the autotuner or `schedule`).
+ * (lanes per env and envs per wavefront chosen per robot count by the
+ * autotuner or `schedule`).
  * robots_per_env is a HOST array [E] of counts in 2..16; the robot arrays of a
  * mixed batch are laid out env after env (robot_offset = prefix sum).
  * ------------------------------------------------------------------------- */
@@ -326,6 +327,10 @@ typedef struct {
   int32_t block_threads;     /* 64..256, multiple of 64; 0 = 256 */
   int32_t lanes_per_env[17]; /* indexed by N: power of two >= N, <= 16; 0 = smallest */
   int32_t qp_iters[17];      /* indexed by N: active-set iteration cap; 0 = 8N+32 */
+  int32_t envs_per_wave[17]; /* indexed by N: envs sharing a wavefront, 1..64/lanes;
+                                0 = 64/lanes (a wavefront runs the solver stages any
+                                of its envs needs, so fewer envs per wavefront run
+                                fewer of them per env, on more wavefronts) */
 } rs_schedule;
 
 rs_status rs_plan_create(rs_ctx *ctx, int32_t num_envs, const int32_t *robots_per_env,
@@ -368,8 +373,9 @@ int64_t rs_plan_obs_offset(const rs_plan *plan, int32_t env);
  * sampler, half packed in a tight cluster so the certificate binds) and times
  * env_run over `steps` steps (best of 3) under candidate schedules, by
  * coordinate descent from the default schedule: block size in {64, 128, 256},
- * then per size lanes per env (envs per wavefront = 64 / lanes) doubled,
- * then the active-set iteration cap in {2N+4, 4N+8}. A change is kept when
+ * then per size lanes per env doubled, envs per wavefront in {1/2, 1/4, 1/8}
+ * of a full tile (at least 1) and the active-set iteration cap in
+ * {2N+4, 4N+8}. A change is kept when
  * no certificate solve of its run stopped at the iteration cap (so every
  * step reached the exact minimiser), every final position matches the
  * default-schedule, widest-cap reference within steps * dt * tol (tol in
@@ -382,6 +388,13 @@ int64_t rs_plan_obs_offset(const rs_plan *plan, int32_t env);
  * ------------------------------------------------------------------------- */
 rs_status rs_autotune(rs_ctx *ctx, const rs_params *p, const int32_t *robots, int32_t count,
                       int32_t envs, int32_t steps, double tol, rs_schedule *out);
+/* The same search on the caller's own mixed batch (plan + b, FP32): every
+ * candidate runs `steps` env_run steps from a copy of b's state, which is
+ * left unchanged; the schedule is stored in the context and returned in out
+ * (may be NULL). Allocates device scratch for the copy (RS_ERR_OUT_OF_MEMORY
+ * if that fails). */
+rs_status rs_autotune_batch(rs_ctx *ctx, const rs_params *p, const rs_plan *plan,
+                            const rs_batch *b, int32_t steps, double tol, rs_schedule *out);
 rs_status rs_get_schedule(rs_ctx *ctx, rs_schedule *out);
 
 /* ---------------------------------------------------------------------------

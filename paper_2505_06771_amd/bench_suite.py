@@ -151,20 +151,29 @@ def uneven_8192(R, ctx, seed=0, steps=1000, autotune=True):
         R.env_reset_mixed(ctx, p, plan, b)
         R.env_run(ctx, p, plan, b, 5)
         _sync()
+        ctx.qp_failures(reset=True)
         t0 = time.perf_counter()
         R.env_run(ctx, p, plan, b, steps, t_global0=0)
         _sync()
         dt = time.perf_counter() - t0
         out[f"robot_steps_per_s_{label}"] = robots * steps / dt
         out[f"ms_{label}"] = dt * 1e3
+        # certificate solves of the timed run that were infeasible or stopped
+        # at the schedule's iteration cap (a capped solve is not exact)
+        out[f"qp_infeasible_{label}"], out[f"qp_capped_{label}"] = ctx.qp_failures(reset=True)
 
     persistent(None, "persistent_default")
     if autotune:
+        # tuned on the benchmark's own batch (the reset state), 50 steps
+        plan = R.Plan(ctx, counts)
+        b = R.Batch.empty(8192, 0, total_robots=plan.total_robots)
+        R.env_reset_mixed(ctx, p, plan, b)
         t0 = time.perf_counter()
-        s = R.autotune(ctx, p, [2, 4, 6, 8, 12], envs=2048, steps=50, tol=1e-4)
+        s = R.autotune_batch(ctx, p, plan, b, steps=50, tol=1e-4)
         out["autotune_s"] = time.perf_counter() - t0
         out["schedule"] = {"block_threads": s.block_threads,
                            "lanes_per_env": {n: s.lanes_per_env[n] for n in (2, 4, 6, 8, 12)},
+                           "envs_per_wave": {n: s.envs_per_wave[n] for n in (2, 4, 6, 8, 12)},
                            "qp_iters": {n: s.qp_iters[n] for n in (2, 4, 6, 8, 12)}}
         persistent(s, "persistent_autotuned")
     # plain: one uniform batch per size, 5 env_step launches per step

@@ -122,24 +122,36 @@ int lanes_for(const rs_schedule &sched, int n) {
   return pow2_group(n);
 }
 
+int envs_per_wave_for(const rs_schedule &sched, int n) {
+  const int full = 64 / lanes_for(sched, n);
+  const int c = sched.envs_per_wave[n];
+  return (c >= 1 && c <= full) ? c : full;
+}
+
 void build_tiles(const std::vector<int32_t> &envs, const std::vector<int32_t> &nrob_of,
                  const rs_schedule &sched, std::vector<int32_t> &tiles,
                  std::vector<int32_t> &items) {
+  // tiles hold envs of one (lanes, envs-per-wavefront) class, by robot count
+  auto cls = [&](int32_t e) {
+    const int n = nrob_of[e];
+    return lanes_for(sched, n) * 128 + envs_per_wave_for(sched, n);
+  };
   std::vector<int32_t> order(envs);
   std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-    const int ga = lanes_for(sched, nrob_of[a]), gb = lanes_for(sched, nrob_of[b]);
-    if (ga != gb) return ga < gb;
+    const int ca = cls(a), cb = cls(b);
+    if (ca != cb) return ca < cb;
     return nrob_of[a] < nrob_of[b];
   });
   tiles.clear();
   items.clear();
   size_t k = 0;
   while (k < order.size()) {
+    const int c0 = cls(order[k]);
     const int g = lanes_for(sched, nrob_of[order[k]]);
-    const int cap = 64 / g;
+    const int cap = envs_per_wave_for(sched, nrob_of[order[k]]);
     const int first = (int)items.size();
     int count = 0;
-    while (k < order.size() && count < cap && lanes_for(sched, nrob_of[order[k]]) == g) {
+    while (k < order.size() && count < cap && cls(order[k]) == c0) {
       items.push_back(order[k]);
       ++k;
       ++count;
@@ -373,24 +385,25 @@ rs_status rs_get_schedule(rs_ctx *ctx, rs_schedule *out) {
 // ---------------------------------------------------------------------------
 // Autotuner
 // ---------------------------------------------------------------------------
-rs_status rs_autotune(rs_ctx *ctx, const rs_params *p, const int32_t *robots, int32_t count,
-                      int32_t envs, int32_t steps, double tol, rs_schedule *out) {
-  RS_CHECK_ARG(ctx != nullptr && robots != nullptr && count >= 1, "ctx/robots invalid");
-  RS_CHECK_ARG(envs >= 1 && steps >= 1 && tol > 0, "envs, steps, tol must be > 0");
-  rs_status s = check_params(p);
-  if (s != RS_OK) return s;
-  RS_CHECK_ARG(p->dtype == RS_F32 && action_driven(p->controller),
-               "autotune runs the FP32 path of an action-driven controller");
+}  // extern "C"
 
-  for (int32_t k = 0; k < count; ++k)
-    RS_CHECK_ARG(robots[k] >= 2 && robots[k] <= RS_MAX_ROBOTS, "robots[%d] = %d outside 2..16",
-                 k, robots[k]);
-  // the mixed workload: `envs` envs of every listed size, interleaved
-  const int64_t E64 = (int64_t)envs * count;
-  RS_CHECK_ARG(E64 < (1 << 24), "envs * count too large for the autotuner");
-  const int32_t E = (int32_t)E64;
-  std::vector<int32_t> counts(E);
-  for (int32_t e = 0; e < E; ++e) counts[e] = robots[e % count];
+namespace rs {
+
+// Schedule search over env_run launches of `steps` steps on a pristine state
+// (the caller's batch `src`, or with src NULL the synthetic workload: the
+// reset sampler for every other env, a tight cluster of pitch 0.2 m around the
+// arena centre, where the certificate binds, for the rest). A candidate passes
+// when no certificate of its first run stopped at the iteration cap (every
+// step then reached the exact minimiser) and its final positions match the
+// default-schedule, widest-cap reference within steps * dt * tol; it is kept
+// when it is also at least 2% faster than the best so far.
+static rs_status autotune_impl(rs_ctx *ctx, const rs_params *p, const std::vector<int32_t> &counts,
+                               const rs_batch *src, int32_t steps, double tol, rs_schedule *out) {
+  const int32_t E = (int32_t)counts.size();
+  std::vector<int32_t> sizes;
+  for (int32_t n : counts)
+    if (std::find(sizes.begin(), sizes.end(), n) == sizes.end()) sizes.push_back(n);
+  std::sort(sizes.begin(), sizes.end());
   size_t R = 0;
   for (int32_t e = 0; e < E; ++e) R += (size_t)counts[e];
 
@@ -402,25 +415,23 @@ rs_status rs_autotune(rs_ctx *ctx, const rs_params *p, const int32_t *robots, in
   float *dbuf = nullptr;
   int32_t *ibuf = nullptr;
   rs_status result = RS_OK;
+  // dbuf: working state [5R] then the pristine copy [5R]; ibuf: working
+  // step/episode [2E], pristine [2E], then the tuner's failure counters
   if (hipMalloc(&dbuf, 10 * R * sizeof(float)) != hipSuccess ||
-      hipMalloc(&ibuf, (2 * (size_t)E + 4) * sizeof(int32_t)) != hipSuccess) {
+      hipMalloc(&ibuf, (4 * (size_t)E + 4) * sizeof(int32_t)) != hipSuccess) {
     set_error("autotune allocation failed");
     result = RS_ERR_OUT_OF_MEMORY;
   }
   rs_batch b;
   std::memset(&b, 0, sizeof(b));
-  float *init = dbuf ? dbuf + 5 * R : nullptr;  // pristine copy of the 5 fields
+  float *init = dbuf ? dbuf + 5 * R : nullptr;
+  int32_t *init_i = ibuf ? ibuf + 2 * E : nullptr;
   std::vector<float> rx(R), ry(R), cx(R), cy(R);
   auto restore = [&]() {
     (void)hipMemcpyAsync(dbuf, init, 5 * R * 4, hipMemcpyDeviceToDevice, st);
-    (void)hipMemsetAsync(ibuf, 0, 2 * (size_t)E * sizeof(int32_t), st);
+    (void)hipMemcpyAsync(ibuf, init_i, 2 * (size_t)E * sizeof(int32_t), hipMemcpyDeviceToDevice, st);
   };
-  // the tuner's own failure counters ([0] infeasible, [1] capped solves),
-  // behind the env flags
-  unsigned long long *fail = ibuf ? reinterpret_cast<unsigned long long *>(ibuf + 2 * E) : nullptr;
-  // run `sched` (min over reps); a candidate passes when no certificate of
-  // its first run stopped at the iteration cap (every step then reached the
-  // exact minimiser) and its final positions match the reference
+  unsigned long long *fail = ibuf ? reinterpret_cast<unsigned long long *>(ibuf + 4 * E) : nullptr;
   auto measure = [&](const rs_schedule &sched, bool check, float &ms) -> bool {
     rs_plan *pl = nullptr;
     if (rs_plan_create(ctx, E, counts.data(), &sched, &pl) != RS_OK) return false;
@@ -468,37 +479,45 @@ rs_status rs_autotune(rs_ctx *ctx, const rs_params *p, const int32_t *robots, in
     b.x = f; b.y = f + R; b.theta = f + 2 * R; b.goal_x = f + 3 * R; b.goal_y = f + 4 * R;
     b.step = ibuf;
     b.episode = ibuf + E;
-    // start states: the reset sampler for every other env, a tight cluster of
-    // pitch 0.2 m around the arena centre (the certificate binds) for the rest
-    rs_plan *ref_plan = nullptr;
-    result = rs_plan_create(ctx, E, counts.data(), &best, &ref_plan);
-    if (result == RS_OK) {
-      (void)hipMemsetAsync(ibuf, 0, 2 * (size_t)E * sizeof(int32_t), st);
-      result = env_reset_mixed(ctx, p, ref_plan, &b, nullptr, st);
+    if (src) {
+      const void *fs[5] = {src->x, src->y, src->theta, src->goal_x, src->goal_y};
+      for (int k = 0; k < 5; ++k)
+        (void)hipMemcpyAsync(init + k * R, fs[k], R * 4, hipMemcpyDeviceToDevice, st);
+      (void)hipMemcpyAsync(init_i, src->step, (size_t)E * 4, hipMemcpyDeviceToDevice, st);
+      (void)hipMemcpyAsync(init_i + E, src->episode, (size_t)E * 4, hipMemcpyDeviceToDevice, st);
       (void)hipStreamSynchronize(st);
-      std::vector<float> hx(R), hy(R);
-      (void)hipMemcpy(hx.data(), b.x, R * 4, hipMemcpyDeviceToHost);
-      (void)hipMemcpy(hy.data(), b.y, R * 4, hipMemcpyDeviceToHost);
-      size_t off = 0;
-      for (int32_t e = 0; e < E; ++e) {
-        const int n = counts[e];
-        if (e & 1) {
-          const int side = (int)std::ceil(std::sqrt((double)n));
-          for (int i = 0; i < n; ++i) {
-            hx[off + i] = -0.3f + 0.2f * (float)(i % side);
-            hy[off + i] = -0.3f + 0.2f * (float)(i / side);
+    } else {
+      rs_plan *ref_plan = nullptr;
+      result = rs_plan_create(ctx, E, counts.data(), &best, &ref_plan);
+      if (result == RS_OK) {
+        (void)hipMemsetAsync(ibuf, 0, 2 * (size_t)E * sizeof(int32_t), st);
+        result = env_reset_mixed(ctx, p, ref_plan, &b, nullptr, st);
+        (void)hipStreamSynchronize(st);
+        std::vector<float> hx(R), hy(R);
+        (void)hipMemcpy(hx.data(), b.x, R * 4, hipMemcpyDeviceToHost);
+        (void)hipMemcpy(hy.data(), b.y, R * 4, hipMemcpyDeviceToHost);
+        size_t off = 0;
+        for (int32_t e = 0; e < E; ++e) {
+          const int n = counts[e];
+          if (e & 1) {
+            const int side = (int)std::ceil(std::sqrt((double)n));
+            for (int i = 0; i < n; ++i) {
+              hx[off + i] = -0.3f + 0.2f * (float)(i % side);
+              hy[off + i] = -0.3f + 0.2f * (float)(i / side);
+            }
           }
+          off += (size_t)n;
         }
-        off += (size_t)n;
+        (void)hipMemcpy(b.x, hx.data(), R * 4, hipMemcpyHostToDevice);
+        (void)hipMemcpy(b.y, hy.data(), R * 4, hipMemcpyHostToDevice);
+        (void)hipMemcpy(init, dbuf, 5 * R * 4, hipMemcpyDeviceToDevice);
+        (void)hipMemcpy(init_i, ibuf, 2 * (size_t)E * 4, hipMemcpyDeviceToDevice);
+        rs_plan_destroy(ref_plan);
       }
-      (void)hipMemcpy(b.x, hx.data(), R * 4, hipMemcpyHostToDevice);
-      (void)hipMemcpy(b.y, hy.data(), R * 4, hipMemcpyHostToDevice);
-      (void)hipMemcpy(init, dbuf, 5 * R * 4, hipMemcpyDeviceToDevice);
-      rs_plan_destroy(ref_plan);
     }
     // reference positions: the default schedule with the widest iteration cap
     rs_schedule ref = best;
-    for (int32_t k = 0; k < count; ++k) ref.qp_iters[robots[k]] = 8 * robots[k] + 32;
+    for (int32_t n : sizes) ref.qp_iters[n] = 8 * n + 32;
     float ref_ms = 0.f;
     if (result == RS_OK && measure(ref, false, ref_ms)) {
       (void)hipMemcpy(rx.data(), b.x, R * 4, hipMemcpyDeviceToHost);
@@ -508,9 +527,8 @@ rs_status rs_autotune(rs_ctx *ctx, const rs_params *p, const int32_t *robots, in
                 "iteration cap (8N+32)");
       result = RS_ERR_DEVICE;
     }
-    // coordinate descent from the default schedule: block size, then lanes
-    // per env and iteration cap size by size; a change is kept only when it
-    // passes the check and is at least 2% faster than the best so far
+    // coordinate descent from the default schedule: block size, then per
+    // size lanes per env, envs per wavefront and the iteration cap
     float best_ms = 0.f;
     if (result == RS_OK && !measure(best, true, best_ms)) result = RS_ERR_DEVICE;
     auto consider = [&](const rs_schedule &cand) {
@@ -527,12 +545,18 @@ rs_status rs_autotune(rs_ctx *ctx, const rs_params *p, const int32_t *robots, in
         c.block_threads = blk;
         consider(c);
       }
-      for (int32_t k = 0; k < count; ++k) {
-        const int n = robots[k];
+      for (int32_t n : sizes) {
         const int g0 = pow2_group(n);
         if (2 * g0 <= 16) {
           rs_schedule c = best;
           c.lanes_per_env[n] = 2 * g0;
+          consider(c);
+        }
+        const int full = 64 / lanes_for(best, n);
+        for (int div = 2; div <= 8; div *= 2) {
+          if (full / div < 1) break;
+          rs_schedule c = best;
+          c.envs_per_wave[n] = full / div;
           consider(c);
         }
         const int caps[2] = {2 * n + 4, 4 * n + 8};
@@ -543,9 +567,9 @@ rs_status rs_autotune(rs_ctx *ctx, const rs_params *p, const int32_t *robots, in
         }
       }
       // report the effective values for the tuned sizes
-      for (int32_t k = 0; k < count; ++k) {
-        const int n = robots[k];
+      for (int32_t n : sizes) {
         best.lanes_per_env[n] = lanes_for(best, n);
+        best.envs_per_wave[n] = envs_per_wave_for(best, n);
         if (best.qp_iters[n] <= 0) best.qp_iters[n] = 8 * n + 32;
       }
       ctx->sched = best;
@@ -558,6 +582,37 @@ rs_status rs_autotune(rs_ctx *ctx, const rs_params *p, const int32_t *robots, in
   (void)hipStreamDestroy(st);
   if (out) *out = ctx->sched;
   return result;
+}
+
+}  // namespace rs
+
+extern "C" {
+
+rs_status rs_autotune(rs_ctx *ctx, const rs_params *p, const int32_t *robots, int32_t count,
+                      int32_t envs, int32_t steps, double tol, rs_schedule *out) {
+  RS_CHECK_ARG(ctx != nullptr && robots != nullptr && count >= 1, "ctx/robots invalid");
+  RS_CHECK_ARG(envs >= 1 && steps >= 1 && tol > 0, "envs, steps, tol must be > 0");
+  rs_status s = check_params(p);
+  if (s != RS_OK) return s;
+  RS_CHECK_ARG(p->dtype == RS_F32 && action_driven(p->controller),
+               "autotune runs the FP32 path of an action-driven controller");
+  for (int32_t k = 0; k < count; ++k)
+    RS_CHECK_ARG(robots[k] >= 2 && robots[k] <= RS_MAX_ROBOTS, "robots[%d] = %d outside 2..16",
+                 k, robots[k]);
+  // the mixed workload: `envs` envs of every listed size, interleaved
+  const int64_t E64 = (int64_t)envs * count;
+  RS_CHECK_ARG(E64 < (1 << 24), "envs * count too large for the autotuner");
+  std::vector<int32_t> counts((size_t)E64);
+  for (int64_t e = 0; e < E64; ++e) counts[(size_t)e] = robots[e % count];
+  return autotune_impl(ctx, p, counts, nullptr, steps, tol, out);
+}
+
+rs_status rs_autotune_batch(rs_ctx *ctx, const rs_params *p, const rs_plan *plan,
+                            const rs_batch *b, int32_t steps, double tol, rs_schedule *out) {
+  rs_status s = check_mixed(ctx, p, plan, b);
+  if (s != RS_OK) return s;
+  RS_CHECK_ARG(steps >= 1 && tol > 0, "steps and tol must be > 0");
+  return autotune_impl(ctx, p, plan->robots_host, b, steps, tol, out);
 }
 
 }  // extern "C"

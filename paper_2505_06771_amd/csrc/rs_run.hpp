@@ -50,5 +50,7 @@ void build_tiles(const std::vector<int32_t> &envs, const std::vector<int32_t> &n
                  std::vector<int32_t> &items);
 
 int lanes_for(const rs_schedule &sched, int n);
+// Envs per wavefront tile for robot count n (1 .. 64 / lanes_for).
+int envs_per_wave_for(const rs_schedule &sched, int n);
 
 }  // namespace rs

@@ -74,7 +74,7 @@ class RsPolicy(ctypes.Structure):
 
 class RsSchedule(ctypes.Structure):
     _fields_ = [("block_threads", ctypes.c_int32), ("lanes_per_env", ctypes.c_int32 * 17),
-                ("qp_iters", ctypes.c_int32 * 17)]
+                ("qp_iters", ctypes.c_int32 * 17), ("envs_per_wave", ctypes.c_int32 * 17)]
 
 
 class RsRequestInfo(ctypes.Structure):
@@ -140,6 +140,7 @@ def lib():
                           _VP, _VP, _VP]),
         "rs_autotune": (i32, [_VP, P(RsParams), _VP, i32, i32, i32, dbl, P(RsSchedule)]),
         "rs_get_schedule": (i32, [_VP, P(RsSchedule)]),
+        "rs_autotune_batch": (i32, [_VP, P(RsParams), _VP, P(RsBatch), i32, dbl, P(RsSchedule)]),
         "rs_server_create": (i32, [_VP, P(RsParams), i64, i32, P(_VP)]),
         "rs_server_destroy": (i32, [_VP]),
         "rs_request_bytes": (i64, [i32, i32]),
@@ -396,6 +397,16 @@ def autotune(ctx: Context, p: RsParams, robots, envs: int = 4096, steps: int = 5
     out = RsSchedule()
     _check(lib().rs_autotune(ctx.handle, ctypes.byref(p), arr.ctypes.data, arr.size, envs, steps,
                              tol, ctypes.byref(out)))
+    return out
+
+
+def autotune_batch(ctx: Context, p: RsParams, plan: Plan, b: Batch, steps: int = 50,
+                   tol: float = 1e-4) -> RsSchedule:
+    """Autotune on the caller's own mixed batch (its state is left unchanged)."""
+    out = RsSchedule()
+    cb = b.c()
+    _check(lib().rs_autotune_batch(ctx.handle, ctypes.byref(p), plan.handle, ctypes.byref(cb),
+                                   steps, tol, ctypes.byref(out)))
     return out
 
 

@@ -75,7 +75,8 @@ def test_struct_layouts_match_the_header(R, tmp_path):
     fields = {"rs_params": ["seed", "qp_max_iters", "grid", "waypoint_step", "action_noise",
                             "tag_reward", "scenario", "pose_gain_rho", "pose_gain_beta"],
               "rs_batch": ["env_id_base", "episode"],
-              "rs_policy": ["in_dim", "b3"], "rs_schedule": ["qp_iters", "lanes_per_env"],
+              "rs_policy": ["in_dim", "b3"],
+              "rs_schedule": ["qp_iters", "lanes_per_env", "envs_per_wave"],
               "rs_request_info": ["finish_time", "horizon"],
               "rs_server_stats": ["running", "peak_bytes"]}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "robostep.h"', "int main(void){"]

@@ -7,6 +7,8 @@ Parity: one env_run step is compared with the FP64 oracle teacher-forced
 bit for bit; results are identical under every schedule (lanes per env,
 block size) and for an env alone or inside a mixed batch.
 """
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -129,7 +131,8 @@ def test_schedule_independence():
     counts = synth.uneven_sizes(4, 260)
     banner("schedules")
     ref = _run_steps(R, ctx, counts, 12, 25)
-    for blk, wide in [(64, False), (128, True), (256, True)]:
+    for blk, wide, div in [(64, False, 1), (128, True, 1), (256, True, 1), (256, False, 4),
+                           (128, False, 64)]:
         s = R.RsSchedule()
         s.block_threads = blk
         for n in range(2, 17):
@@ -137,6 +140,7 @@ def test_schedule_independence():
             while g < n:
                 g *= 2
             s.lanes_per_env[n] = min(16, 2 * g) if wide else g
+            s.envs_per_wave[n] = max(1, (64 // s.lanes_per_env[n]) // div)
         got = _run_steps(R, ctx, counts, 12, 25, schedule=s)
         np.testing.assert_array_equal(got[0], ref[0])
         np.testing.assert_array_equal(got[1], ref[1])
@@ -164,6 +168,7 @@ def test_autotune_returns_valid_schedule():
         g = s.lanes_per_env[n]
         assert g >= n and g in (4, 8, 16)
         assert s.qp_iters[n] in (2 * n + 4, 4 * n + 8, 8 * n + 32)
+        assert 1 <= s.envs_per_wave[n] <= 64 // g
     assert s.block_threads in (64, 128, 256)
 
 
@@ -217,3 +222,26 @@ def test_autotuned_schedule_matches_oracle(orc):
     assert q[:, R.QPS_ACTIVE_SET:R.QPS_GENERAL + 1].sum() > 0
     print("tuned schedule:", {n: (s.lanes_per_env[n], s.qp_iters[n]) for n in sizes},
           "block", s.block_threads, "stages", q[:, :R.QPS_ITERATIONS].sum(axis=0).tolist())
+
+
+def test_autotune_on_the_callers_batch_leaves_it_unchanged():
+    import torch
+
+    R, ctx = ctx_and_lib()
+    counts = synth.uneven_sizes(7, 400)
+    banner("autotune_batch")
+    plan, b = _mixed_batch(R, ctx, counts, seed=3)
+    before = [host(getattr(b, a)).copy() for a in ("x", "y", "theta", "step", "episode")]
+    s = R.autotune_batch(ctx, R.params(seed=3), plan, b, steps=20, tol=1e-4)
+    torch.cuda.synchronize()
+    after = [host(getattr(b, a)) for a in ("x", "y", "theta", "step", "episode")]
+    for u, v in zip(before, after):
+        np.testing.assert_array_equal(u, v)
+    for n in sorted(set(counts.tolist())):
+        g = s.lanes_per_env[n]
+        assert g >= n and g in (2, 4, 8, 16)
+        assert 1 <= s.envs_per_wave[n] <= 64 // g
+        assert s.qp_iters[n] in (2 * n + 4, 4 * n + 8, 8 * n + 32)
+    got = R.RsSchedule()
+    R.lib().rs_get_schedule(ctx.handle, ctypes.byref(got))
+    assert got.block_threads == s.block_threads
