@@ -206,9 +206,12 @@ def serving(R, ctx, seed=0, count=2000, skip=200, budget=64 << 30, stress_budget
     served path (measured first on a burst) / mean request work. The served
     path runs twice: at the nominal HBM budget and at `stress_budget`, small
     enough that admission queues requests (2 MiB holds one request of the
-    largest size, 4096 envs x 16 robots, 1.45 MB). The plain path serves only
-    the first `plain_count` requests: each runs alone with one launch per
-    step, about a third of a second each."""
+    largest size, 4096 envs x 16 robots, 1.45 MB). Two plain forms serve the
+    same stream in arrival order, one request at a time: every request in one
+    persistent env_run launch (all requests; its saturated capacity is
+    measured on the same burst as the served path's), and every step as its
+    own env_step launch (only the first `plain_count` requests: about a third
+    of a second each)."""
     import torch
 
     from paper_2505_06771_amd import synth
@@ -277,10 +280,56 @@ def serving(R, ctx, seed=0, count=2000, skip=200, budget=64 << 30, stress_budget
             work += r["envs"] * r["robots"] * r["horizon"]
         return lat, time.perf_counter() - start, work
 
+    # plain but fair: FIFO, each request alone in ONE persistent env_run
+    # launch (no per-step launches). Per robot count a 4096-env plan and
+    # state are made up front, so nothing is allocated per request; a
+    # request resets and runs its first `envs` envs (the others take 0 steps)
+    # with the served path's env ids and stream times.
+    import torch as _t
+
+    pre = {}
+    for n in range(3, 17):
+        pl = R.Plan(ctx, np.full(4096, n, np.int32))
+        pre[n] = (pl, R.Batch.empty(4096, 0, total_robots=pl.total_robots))
+    mask = _t.zeros(4096, dtype=_t.uint8, device="cuda")
+    spe = _t.zeros(4096, dtype=_t.int32, device="cuda")
+
+    def plain_one(r):
+        pl, bb = pre[r["robots"]]
+        bb.env_id_base = r["id"] << 20
+        bb.step.zero_()
+        bb.episode.zero_()
+        mask.zero_()
+        mask[:r["envs"]] = 1
+        spe.zero_()
+        spe[:r["envs"]] = r["horizon"]
+        R.env_reset_mixed(ctx, p, pl, bb, mask=mask)
+        R.env_run(ctx, p, pl, bb, r["horizon"], t_global0=0, steps_per_env=spe)
+
+    def run_plain_persistent(rs, honour_arrivals=True):
+        lat = {}
+        start = time.perf_counter()
+        work = 0
+        for r in rs:
+            now = time.perf_counter() - start
+            if honour_arrivals and now < r["arrival"]:
+                time.sleep(r["arrival"] - now)
+            plain_one(r)
+            _sync()
+            lat[r["id"]] = time.perf_counter() - start - r["arrival"]
+            work += r["envs"] * r["robots"] * r["horizon"]
+        return lat, time.perf_counter() - start, work
+
+    # saturated capacity of the plain persistent form on the same burst
+    _, wall_pc, work_pc = run_plain_persistent(probe, honour_arrivals=False)
+    cap_plain = work_pc / wall_pc
+
     lat_s, wall_s, work_s, _ = run_served(budget)
     ls = np.array([lat_s[i] for i in range(skip, count)])
     lat_q, wall_q, work_q, peak_q = run_served(stress_budget)
     lq = np.array([lat_q[i] for i in range(skip, count)])
+    lat_pp, wall_pp, work_pp = run_plain_persistent(reqs)
+    lpp = np.array([lat_pp[i] for i in range(skip, count)])
     n_plain = min(plain_count, count)
     lat_p, wall_p, work_p = run_plain(n_plain)
     lp = np.array([lat_p[i] for i in range(min(skip, n_plain // 2), n_plain)])
@@ -294,6 +343,11 @@ def serving(R, ctx, seed=0, count=2000, skip=200, budget=64 << 30, stress_budget
             "stress_p50_ms": float(np.percentile(lq, 50) * 1e3),
             "stress_p99_ms": float(np.percentile(lq, 99) * 1e3),
             "stress_robot_steps_per_s": work_q / wall_q,
+            "plain_persistent_capacity_robot_steps_per_s": cap_plain,
+            "plain_persistent_requests": count,
+            "plain_persistent_p50_ms": float(np.percentile(lpp, 50) * 1e3),
+            "plain_persistent_p99_ms": float(np.percentile(lpp, 99) * 1e3),
+            "plain_persistent_robot_steps_per_s": work_pp / wall_pp,
             "plain_requests": n_plain,
             "plain_p50_ms": float(np.percentile(lp, 50) * 1e3),
             "plain_p99_ms": float(np.percentile(lp, 99) * 1e3),
