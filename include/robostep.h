@@ -368,6 +368,40 @@ rs_status env_run(rs_ctx *ctx, const rs_params *p, const rs_plan *plan, const rs
 int64_t rs_plan_obs_offset(const rs_plan *plan, int32_t env);
 
 /* ---------------------------------------------------------------------------
+ * env_run_noalloc -- for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc). The same launch and results as env_run with a plan made from
+ * the same robot counts (results do not depend on the schedule), but the work
+ * list that a plan keeps in memory it allocates (robot and observation
+ * offsets, env order, wavefront tiles) is built on `stream` by a small kernel
+ * into one fixed device array of the library (RS_NOALLOC_SCRATCH_BYTES per
+ * device, taken when the code is loaded and held until the process ends).
+ * The call allocates nothing: no hipMalloc, hipFree or allocating library
+ * routine.
+ *  robots_per_env: DEVICE int32 [b->num_envs], each 2..16; b's robot arrays
+ *    are laid out env after env (robot offset = prefix sum of the counts) and
+ *    env e's block of obs_final starts at sum over e' < e of N_e'(2N_e'+4).
+ *  b->num_envs: 1..RS_NOALLOC_MAX_ENVS, else RS_ERR_INVALID_ARG before any
+ *    device work.
+ *  bad_envs: DEVICE int32 [1] (may be NULL): set to the number of envs whose
+ *    count is outside 2..16; when that is nonzero no env is stepped and no
+ *    output is written.
+ *  The schedule (lanes and envs per wavefront, iteration caps, block size) is
+ *  the context's (rs_autotune); failures add to the context's counters. Other
+ *  arguments as env_run.
+ *  Every call on a device shares that device's array: calls that overlap on
+ *  one device (two streams, or two host threads) race; order them on one
+ *  stream.
+ * ------------------------------------------------------------------------- */
+#define RS_NOALLOC_MAX_ENVS 65536
+#define RS_NOALLOC_SCRATCH_BYTES 2098176
+rs_status env_run_noalloc(rs_ctx *ctx, const rs_params *p, const int32_t *robots_per_env,
+                          const rs_batch *b, int32_t steps, const int64_t *t_start,
+                          int64_t t_global0, const int32_t *steps_per_env, float *reward_out,
+                          uint8_t *done_out, float *reward_sum, float *obs_final,
+                          int32_t *qp_stats, int32_t *bad_envs, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Autotuner: builds the mixed workload of `envs` synthetic envs of every robot
  * count in `robots` (host [count], each 2..16; half drawn by the reset
  * sampler, half packed in a tight cluster so the certificate binds) and times

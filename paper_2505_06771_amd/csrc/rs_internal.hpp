@@ -84,6 +84,10 @@ namespace rs {
 
 rs_status check_params(const rs_params *p);
 
+// Looks up this device's copy of env_run_noalloc's work-list array (once per
+// device, with the device current; called by rs_create).
+hipError_t noalloc_setup(int device);
+
 // Controllers whose nominal command comes from a per-robot action.
 inline bool action_driven(int controller) {
   return controller == RS_CTRL_DISCRETE || controller == RS_CTRL_WAYPOINT ||

@@ -418,6 +418,7 @@ rs_status rs_create(int device, rs_ctx **out) {
   c->num_cus = prop.multiProcessorCount;
   hipError_t he = hipMalloc((void **)&c->qp_fail, 2 * sizeof(unsigned long long));
   if (he == hipSuccess) he = hipMemset(c->qp_fail, 0, 2 * sizeof(unsigned long long));
+  if (he == hipSuccess) he = rs::noalloc_setup(device);
   if (he != hipSuccess) {
     if (c->qp_fail) (void)hipFree(c->qp_fail);
     delete c;

@@ -93,6 +93,7 @@ __global__ __launch_bounds__(256) void k_env_run(RunArgs A) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int tile = blockIdx.x * (blockDim.x >> 6) + wave;
   if (tile >= A.num_tiles) return;
+  if (A.num_tiles_dev && tile >= *A.num_tiles_dev) return;
   const int4 td = A.tiles[tile];
   char *mine = lds + (size_t)wave * kMaxWaveLds;
   switch (td.x) {

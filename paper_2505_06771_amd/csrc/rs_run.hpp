@@ -13,7 +13,8 @@ struct RunArgs {
   SimConst<float> C;
   int E;           // rows of reward_out/done_out
   int steps;       // step budget of this launch
-  int num_tiles;
+  int num_tiles;           // tiles of the launch (an upper bound when num_tiles_dev is set)
+  const int32_t *num_tiles_dev;  // device tile count written by an earlier kernel (may be NULL)
   uint32_t env_base;
   uint32_t t0;
   const int4 *tiles;       // {G, first item, count, unused}

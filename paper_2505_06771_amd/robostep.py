@@ -138,6 +138,8 @@ def lib():
         "env_reset_mixed": (i32, [_VP, P(RsParams), _VP, P(RsBatch), _VP, _VP]),
         "env_run": (i32, [_VP, P(RsParams), _VP, P(RsBatch), i32, _VP, i64, _VP, _VP, _VP, _VP,
                           _VP, _VP, _VP]),
+        "env_run_noalloc": (i32, [_VP, P(RsParams), _VP, P(RsBatch), i32, _VP, i64, _VP, _VP,
+                                  _VP, _VP, _VP, _VP, _VP, _VP]),
         "rs_autotune": (i32, [_VP, P(RsParams), _VP, i32, i32, i32, dbl, P(RsSchedule)]),
         "rs_get_schedule": (i32, [_VP, P(RsSchedule)]),
         "rs_autotune_batch": (i32, [_VP, P(RsParams), _VP, P(RsBatch), i32, dbl, P(RsSchedule)]),
@@ -387,6 +389,24 @@ def env_run(ctx: Context, p: RsParams, plan: Plan, b: Batch, steps: int, t_globa
                          _ptr(t_start), t_global0, _ptr(steps_per_env), _ptr(reward_out),
                          _ptr(done_out), _ptr(reward_sum), _ptr(obs_final), _ptr(qp_stats),
                          _stream(stream)))
+
+
+def env_run_noalloc(ctx: Context, p: RsParams, robots_per_env, b: Batch, steps: int,
+                    t_global0: int = 0, t_start=None, steps_per_env=None, reward_out=None,
+                    done_out=None, reward_sum=None, obs_final=None, qp_stats=None, bad_envs=None,
+                    stream=None):
+    """env_run without a plan: robots_per_env is a device int32 tensor [E];
+    bad_envs (device int32 [1], optional) receives the number of envs whose
+    count is outside 2..16 (then nothing runs). Allocates nothing."""
+    cb = b.c()
+    _check(lib().env_run_noalloc(ctx.handle, ctypes.byref(p), _ptr(robots_per_env),
+                                 ctypes.byref(cb), steps, _ptr(t_start), t_global0,
+                                 _ptr(steps_per_env), _ptr(reward_out), _ptr(done_out),
+                                 _ptr(reward_sum), _ptr(obs_final), _ptr(qp_stats),
+                                 _ptr(bad_envs), _stream(stream)))
+
+
+NOALLOC_MAX_ENVS = 65536
 
 
 def autotune(ctx: Context, p: RsParams, robots, envs: int = 4096, steps: int = 50,

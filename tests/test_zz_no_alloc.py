@@ -1,0 +1,143 @@
+"""GPU tests of env_run_noalloc, the env_run variant that allocates nothing:
+its work list lives in one fixed device array of the library, rebuilt on the
+stream by every call from a device array of robot counts.
+
+Its results must equal env_run's (with a plan made from the same counts) bit
+for bit: same state, rewards, done flags, final observations and certificate
+statistics. Two calls in a row, the second on a smaller batch, check that
+the shared array is rebuilt rather than reused; counts outside 2..16 are
+reported through bad_envs and leave everything untouched.
+"""
+import numpy as np
+import pytest
+
+from paper_2505_06771_amd import synth
+from tests.gpu_util import banner, ctx_and_lib, host
+
+pytestmark = pytest.mark.gpu
+
+ALL_SIZES = tuple(range(2, 17))
+
+
+def _counts(seed, E):
+    return synth.uneven_sizes(seed, E, sizes=ALL_SIZES, proportions=(1 / 15,) * 15)
+
+
+def _state_pair(R, ctx, counts, seed, env_id_base):
+    """A plan, a reset batch and an identical copy of it."""
+    plan = R.Plan(ctx, counts)
+    b = R.Batch.empty(len(counts), 0, env_id_base=env_id_base, total_robots=plan.total_robots)
+    R.env_reset_mixed(ctx, R.params(seed=seed), plan, b)
+    c = R.Batch(*(t.clone() for t in (b.x, b.y, b.theta, b.goal_x, b.goal_y, b.step, b.episode)),
+                0, env_id_base)
+    return plan, b, c
+
+
+def _outputs(R, counts, steps):
+    import torch
+
+    E = len(counts)
+    obs_total = int(sum(int(n) * (2 * int(n) + 4) for n in counts))
+    return {"reward_out": torch.full((steps, E), -7.0, device="cuda"),
+            "done_out": torch.full((steps, E), 9, dtype=torch.uint8, device="cuda"),
+            "reward_sum": torch.zeros(E, device="cuda"),
+            "obs_final": torch.full((obs_total,), -5.0, device="cuda"),
+            "qp_stats": torch.zeros((E, R.QPS_COUNT), dtype=torch.int32, device="cuda")}
+
+
+def _compare(R, ctx, counts, seed, steps, env_id_base=0, budgets=False, **extra):
+    import torch
+
+    E = len(counts)
+    plan, b, c = _state_pair(R, ctx, counts, seed, env_id_base)
+    p = R.params(seed=seed, **extra)
+    rng = np.random.default_rng(seed)
+    kw = {}
+    if budgets:
+        kw["t_start"] = torch.from_numpy(rng.integers(0, 10_000, E).astype(np.int64)).cuda()
+        kw["steps_per_env"] = torch.from_numpy(rng.integers(0, steps + 1, E).astype(np.int32)).cuda()
+    # step counters near the time limit so that resets happen inside the run
+    near = torch.from_numpy(rng.integers(500 - steps, 500, E).astype(np.int32)).cuda()
+    b.step.copy_(near)
+    c.step.copy_(near)
+    ref, got = _outputs(R, counts, steps), _outputs(R, counts, steps)
+    bad = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    counts_dev = torch.from_numpy(np.asarray(counts, np.int32)).cuda()
+    R.env_run(ctx, p, plan, b, steps, t_global0=77, **kw, **ref)
+    R.env_run_noalloc(ctx, p, counts_dev, c, steps, t_global0=77, bad_envs=bad, **kw, **got)
+    torch.cuda.synchronize()
+    assert int(host(bad)[0]) == 0
+    for name in ("x", "y", "theta", "goal_x", "goal_y", "step", "episode"):
+        np.testing.assert_array_equal(host(getattr(c, name)), host(getattr(b, name)), err_msg=name)
+    for name in ref:
+        np.testing.assert_array_equal(host(got[name]), host(ref[name]), err_msg=name)
+    assert (host(ref["done_out"]) == 1).any()  # resets were exercised
+    if budgets:
+        assert (host(ref["reward_out"]) == -7.0).any()  # rows past an env's budget untouched
+    plan.close()
+
+
+def test_noalloc_equals_env_run_two_calls_shrinking():
+    """The largest batch the array holds, then a smaller one with per-env
+    budgets and stream times (several tiles of every robot count, ragged
+    tails)."""
+    R, ctx = ctx_and_lib()
+    big = _counts(11, R.NOALLOC_MAX_ENVS)
+    banner(f"env_run_noalloc E={len(big)}")
+    _compare(R, ctx, big, seed=3, steps=3)
+    small = _counts(12, 1237)
+    banner(f"env_run_noalloc E={len(small)} after the largest")
+    _compare(R, ctx, small, seed=4, steps=12, env_id_base=5, budgets=True)
+
+
+@pytest.mark.parametrize("extra", [{"controller": 2, "action_noise": 0.05}, {"controller": 3},
+                                   {"scenario": 1}],
+                         ids=["waypoint_noise", "pose", "predator_prey"])
+def test_noalloc_equals_env_run_controllers(extra):
+    R, ctx = ctx_and_lib()
+    banner(f"env_run_noalloc {extra}")
+    _compare(R, ctx, _counts(21, 333), seed=8, steps=10, **extra)
+    _compare(R, ctx, _counts(22, 70), seed=9, steps=10, **extra)
+
+
+def test_noalloc_single_env_and_one_size():
+    R, ctx = ctx_and_lib()
+    banner("env_run_noalloc single env, one size")
+    _compare(R, ctx, np.array([16], np.int32), seed=2, steps=5)
+    _compare(R, ctx, np.full(129, 2, np.int32), seed=2, steps=5)
+
+
+def test_noalloc_bad_counts_leave_everything_untouched():
+    import torch
+
+    R, ctx = ctx_and_lib()
+    counts = _counts(31, 200)
+    plan, b, c = _state_pair(R, ctx, counts, seed=5, env_id_base=0)
+    before = [host(t).copy() for t in (c.x, c.theta, c.step, c.episode)]
+    wrong = np.asarray(counts, np.int32).copy()
+    wrong[17], wrong[150] = 17, 1
+    out = _outputs(R, counts, 4)
+    bad = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    banner("env_run_noalloc bad counts")
+    R.env_run_noalloc(ctx, R.params(seed=5), torch.from_numpy(wrong).cuda(), c, 4, bad_envs=bad,
+                      **out)
+    torch.cuda.synchronize()
+    assert int(host(bad)[0]) == 2
+    for a, t in zip(before, (c.x, c.theta, c.step, c.episode)):
+        np.testing.assert_array_equal(host(t), a)
+    assert (host(out["reward_out"]) == -7.0).all() and (host(out["obs_final"]) == -5.0).all()
+    assert (host(out["qp_stats"]) == 0).all()
+    # the next call with valid counts runs normally
+    _compare(R, ctx, counts, seed=5, steps=4)
+    plan.close()
+
+
+def test_noalloc_rejects_more_envs_than_the_array_holds():
+    import torch
+
+    R, ctx = ctx_and_lib()
+    E = R.NOALLOC_MAX_ENVS + 1
+    b = R.Batch.empty(E, 0, total_robots=2 * E)
+    counts = torch.full((E,), 2, dtype=torch.int32, device="cuda")
+    with pytest.raises(RuntimeError, match="65536"):
+        R.env_run_noalloc(ctx, R.params(), counts, b, 1)
