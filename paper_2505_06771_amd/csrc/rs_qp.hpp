@@ -32,7 +32,7 @@
 
 namespace rs {
 
-template <typename T, int G> struct QPScratch {
+template <typename T, int G> struct alignas(16) QPScratch {
   int act[2 * G];           // active pair rows: a | b << 8, a < b
   T dx[2 * G], dy[2 * G];   // D = p_a - p_b of each active row
   T lam[2 * G];             // multipliers (objective 1/2 |u - u_nom|^2)
@@ -946,10 +946,27 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
   T cdx[KH], cdy[KH], cb[KH], crn[KH], snk[KH];
   int cpid[KH];
   bool coincide = false;
+  // FP32 8-lane groups take the partner's (p, u0) from one 16-byte LDS
+  // exchange in the group's scratch (free here) instead of four DPP
+  // rotations of two moves and a select each
+  constexpr bool kLdsX = std::is_same<T, float>::value && G == 8;
+  float4 *xq = reinterpret_cast<float4 *>(sh);
+  static_assert(!kLdsX || sizeof(QPScratch<T, G>) >= G * (sizeof(float4) + sizeof(float2)),
+                "the exchange fits in the group's scratch");
+  if constexpr (kLdsX) {
+    xq[i] = make_float4(px, py, ux, uy);
+    wave_lds_fence();
+  }
   static_for<1, KH + 1>([&](auto kc) {
     constexpr int K = decltype(kc)::value;
-    const T pxj = grot<G, K>(px, lane), pyj = grot<G, K>(py, lane);
-    const T uxj = grot<G, K>(ux, lane), uyj = grot<G, K>(uy, lane);
+    T pxj, pyj, uxj, uyj;
+    if constexpr (kLdsX) {
+      const float4 v = xq[(i + K) & (G - 1)];
+      pxj = v.x; pyj = v.y; uxj = v.z; uyj = v.w;
+    } else {
+      pxj = grot<G, K>(px, lane); pyj = grot<G, K>(py, lane);
+      uxj = grot<G, K>(ux, lane); uyj = grot<G, K>(uy, lane);
+    }
     const int j = (i + K) & (G - 1);
     const bool valid = on && j < N && !(2 * K == G && i >= KH);
     // D = p_i - p_j as this lane sees the pair. The row's own D runs from
@@ -1196,9 +1213,20 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
       // at u0 (below the threshold), and a pruned row holds anywhere in the
       // speed box, which contains every guess
       bool bad = !ok;
+      float2 *xv = reinterpret_cast<float2 *>(sh) + 2 * G;  // past the scan's exchange
+      if constexpr (kLdsX) {
+        xv[i] = make_float2(nux, nuy);
+        wave_lds_fence();
+      }
       static_for<1, KH + 1>([&](auto kc) {
         constexpr int K = decltype(kc)::value;
-        const T uxj = grot<G, K>(nux, lane), uyj = grot<G, K>(nuy, lane);
+        T uxj, uyj;
+        if constexpr (kLdsX) {
+          const float2 v = xv[(i + K) & (G - 1)];
+          uxj = v.x; uyj = v.y;
+        } else {
+          uxj = grot<G, K>(nux, lane); uyj = grot<G, K>(nuy, lane);
+        }
         const int id = cpid[K - 1];
         const bool guessed = (id == bid) | (two & (id == id2));
         const T sn = (T(2) * (cdx[K - 1] * (uxj - nux) + cdy[K - 1] * (uyj - nuy)) - cb[K - 1]) *
