@@ -951,7 +951,7 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
   // rotations of two moves and a select each
   constexpr bool kLdsX = std::is_same<T, float>::value && G == 8;
   float4 *xq = reinterpret_cast<float4 *>(sh);
-  static_assert(!kLdsX || sizeof(QPScratch<T, G>) >= G * (sizeof(float4) + sizeof(float2)),
+  static_assert(!kLdsX || sizeof(QPScratch<T, G>) >= G * (sizeof(float4) + 2 * sizeof(float2)),
                 "the exchange fits in the group's scratch");
   if constexpr (kLdsX) {
     xq[i] = make_float4(px, py, ux, uy);
@@ -1233,19 +1233,102 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
                      crn[K - 1];
         bad = bad | ((id >= 0) & !guessed & (sn > C.tol_add));
       });
-      const bool accept = !group_any<G>(bad, lane);
+      bool accept = !group_any<G>(bad, lane);
+      bool seeded = !accept && !two && ok;
+      bool second = false;  // accepted on the second guess below
+      int sqa = qa, sqb = qb;
+      if constexpr (kLdsX) {
+        // A rejected one-row guess violates some row r, which shares a robot
+        // with p (only p's robots moved). Second guess: p and r both active
+        // with no bound binding, from their 2 x 2 Gram system, accepted by
+        // the checks of the shared-robot stage (wave-uniform branch: only
+        // wavefronts with such a group pay for it). The guess's commands are
+        // still in the exchange (xv).
+        if (__ballot(seeded) != 0) {
+          T rbest = C.tol_add, rdx = T(0), rdy = T(0), rbb = T(0);
+          int rid = -1;
+          static_for<1, KH + 1>([&](auto kc) {
+            constexpr int K = decltype(kc)::value;
+            const float2 v = xv[(i + K) & (G - 1)];
+            const int id = cpid[K - 1];
+            const T sn = (T(2) * (cdx[K - 1] * (v.x - nux) + cdy[K - 1] * (v.y - nuy)) - cb[K - 1]) *
+                         crn[K - 1];
+            if (seeded && id >= 0 && id != bid && sn > rbest) {
+              rbest = sn;
+              rid = id;
+              rdx = cdx[K - 1];
+              rdy = cdy[K - 1];
+              rbb = cb[K - 1];
+            }
+          });
+          const int wr = group_argmax_lane<G>(rbest, rid >= 0, i);
+          const int src = gbase + (wr < 0 ? 0 : wr);
+          rid = wr < 0 ? -1 : __shfl(rid, src, 64);
+          rdx = __shfl(rdx, src, 64);
+          rdy = __shfl(rdy, src, 64);
+          rbb = __shfl(rbb, src, 64);
+          const bool flipr = wr != (rid >> 4);
+          rdx = flipr ? -rdx : rdx;
+          rdy = flipr ? -rdy : rdy;
+          const int ra = rid >> 4, rb = rid & 15;
+          const bool try2 =
+              seeded && rid >= 0 && (ra == pa || ra == pb || rb == pa || rb == pb);
+          const T c1x = i == pa ? T(-2) * bdx : (i == pb ? T(2) * bdx : T(0));
+          const T c1y = i == pa ? T(-2) * bdy : (i == pb ? T(2) * bdy : T(0));
+          const T c2x = i == ra ? T(-2) * rdx : (i == rb ? T(2) * rdx : T(0));
+          const T c2y = i == ra ? T(-2) * rdy : (i == rb ? T(2) * rdy : T(0));
+          const T g11 = T(8) * (bdx * bdx + bdy * bdy);
+          const T g22 = T(8) * (rdx * rdx + rdy * rdy);
+          const T g12 = gsum<G>(c1x * c2x + c1y * c2y);
+          const T h1 = gsum<G>(c1x * uhx + c1y * uhy) - bbb;
+          const T h2 = gsum<G>(c2x * uhx + c2y * uhy) - rbb;
+          const T det = g11 * g22 - g12 * g12;
+          const T idet = qdiv(T(1), det);
+          const T m1 = (g22 * h1 - g12 * h2) * idet;
+          const T m2 = (g11 * h2 - g12 * h1) * idet;
+          bool ok2 = try2 && det > T(1e-6) * g11 * g22 && m1 >= T(0) && m2 >= T(0);
+          const bool mv = i == pa || i == pb || i == ra || i == rb;
+          const T vx = uhx - m1 * c1x - m2 * c2x;
+          const T vy = uhy - m1 * c1y - m2 * c2y;
+          const bool outb = on && mv && (vx < lox || vx > hix || vy < loy || vy > hiy);
+          ok2 = ok2 && !group_any<G>(outb, lane);
+          const T wx = (on && mv) ? vx : ux, wy = (on && mv) ? vy : uy;  // unmoved: u0
+          float2 *xw = xv + G;  // past the guess's exchange
+          xw[i] = make_float2(wx, wy);
+          wave_lds_fence();
+          bool bad2 = !ok2;
+          static_for<1, KH + 1>([&](auto kc) {
+            constexpr int K = decltype(kc)::value;
+            const float2 v = xw[(i + K) & (G - 1)];
+            const int id = cpid[K - 1];
+            const T sn = (T(2) * (cdx[K - 1] * (v.x - wx) + cdy[K - 1] * (v.y - wy)) - cb[K - 1]) *
+                         crn[K - 1];
+            bad2 = bad2 | ((id >= 0) & (id != bid) & (id != rid) & (sn > C.tol_add));
+          });
+          second = try2 && !group_any<G>(bad2, lane);
+          if (second) {
+            nux = wx;
+            nuy = wy;
+            lam1 = m1;
+            lam2 = m2;
+            sqa = ra;
+            sqb = rb;
+            accept = true;
+            seeded = false;
+          }
+        }
+      }
       // accepted: the guess is the solution; one rejected row with ok: start
       // the loop from u(l) with p active; otherwise from u0 (unchanged)
-      const bool seeded = !accept && !two && ok;
       ux = (accept || seeded) ? nux : ux;
       uy = (accept || seeded) ? nuy : uy;
-      fq = accept ? (two ? 2 : 1) : fq;
-      info.stage = two ? (shared ? kStShared : kStTwoRows) : kStOneRow;
+      fq = accept ? ((two || second) ? 2 : 1) : fq;
+      info.stage = (two || second) ? ((shared || second) ? kStShared : kStTwoRows) : kStOneRow;
       seed = seeded;
       fpa = pa; fpb = pb; fl1 = lam1; fdx = bdx; fdy = bdy;
-      fqa = qa; fqb = qb; fl2 = lam2;
+      fqa = sqa; fqb = sqb; fl2 = lam2;
       run_gi = !accept;
-      info.iters = two ? 2 : 1;
+      info.iters = (two || second) ? 2 : 1;
     }
   }
 
