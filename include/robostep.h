@@ -130,9 +130,12 @@ typedef struct rs_plan rs_plan;
  * [E][RS_QPS_COUNT], accumulated (+=) over every solve of the call, so a
  * caller zeroes them first. Each solve adds 1 to exactly one of slots 0..7:
  * the stage that produced the command (BOX: no row violated at the box clip
- * of the nominal command; ONE_ROW: one violated row, projected in closed
+ * of the nominal command; ONE_ROW: one active row, projected in closed
  * form; TWO_ROWS: two violated rows on four distinct robots; SHARED_ROBOT:
- * two violated rows through one robot, 2 x 2 Gram system; ACTIVE_SET: the
+ * two or three active rows through shared robots with no bound binding,
+ * from their Gram system (FP32 also takes this stage when a one-row guess
+ * is rejected: the guessed row plus the row it violates; and for exactly
+ * three violated rows); ACTIVE_SET: the
  * register-resident dual active-set loop; GENERAL: the general active-set
  * solver with its rows in LDS), or INFEASIBLE (no feasible command) or
  * CAPPED (stopped by the iteration cap or a numerical failure). ITERATIONS

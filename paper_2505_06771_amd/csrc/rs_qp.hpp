@@ -125,7 +125,7 @@ enum : int {
   kStBox = 0,        // no row violated at the box clip u0
   kStOneRow = 1,     // one violated row: closed-form projection
   kStTwoRows = 2,    // two violated rows on four distinct robots
-  kStShared = 3,     // two violated rows through a shared robot (2 x 2 Gram system)
+  kStShared = 3,     // two or three rows through shared robots (Gram system, no bound)
   kStActiveSet = 4,  // register-resident active-set loop
   kStGeneral = 5     // general active-set solver with its rows in LDS
 };
@@ -950,8 +950,11 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
   // exchange in the group's scratch (free here) instead of four DPP
   // rotations of two moves and a select each
   constexpr bool kLdsX = std::is_same<T, float>::value && G == 8;
+  // the FP32 closed-form guesses beyond two rows (every group width alike, so
+  // that results do not depend on the schedule)
+  constexpr bool kGuess = std::is_same<T, float>::value;
   float4 *xq = reinterpret_cast<float4 *>(sh);
-  static_assert(!kLdsX || sizeof(QPScratch<T, G>) >= G * (sizeof(float4) + 2 * sizeof(float2)),
+  static_assert(!kGuess || sizeof(QPScratch<T, G>) >= G * (sizeof(float4) + 3 * sizeof(float2)),
                 "the exchange fits in the group's scratch");
   if constexpr (kLdsX) {
     xq[i] = make_float4(px, py, ux, uy);
@@ -993,8 +996,8 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
 
   // outcome of the closed-form stages: rows accepted (fq = 1 or 2), or a
   // one-row start for the active-set loop (seed)
-  int fq = 0, fpa = -1, fpb = -1, fqa = -1, fqb = -1;
-  T fl1 = T(0), fl2 = T(0), fdx = T(0), fdy = T(0);
+  int fq = 0, fpa = -1, fpb = -1, fqa = -1, fqb = -1, fra = -1, frb = -1;
+  T fl1 = T(0), fl2 = T(0), fl3 = T(0), fdx = T(0), fdy = T(0);
   bool seed = false;
 
   // --- closed-form stages --------------------------------------------------------
@@ -1049,6 +1052,101 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
     }
     if (bid < 0) {
       run_gi = false;  // u0 is the solution
+    } else if (nv == 3 && kGuess) {
+      if constexpr (kGuess) {
+        // Three rows violated at u0 (FP32): guess all three
+        // active with no bound binding, from their 3 x 3 Gram system, and
+        // accept as the two-row stages do; otherwise the loop starts from u0.
+        T sx[2] = {T(0), T(0)}, sy[2] = {T(0), T(0)}, sb[2] = {T(0), T(0)};
+        int sid[2] = {-1, -1};
+        static_for<0, 2>([&](auto rc) {
+          constexpr int R = decltype(rc)::value;
+          T b2 = thr, e2x = T(0), e2y = T(0), beta2 = T(0);
+          int id2 = -1;
+          static_for<1, KH + 1>([&](auto kc) {
+            constexpr int K = decltype(kc)::value;
+            const int id = cpid[K - 1];
+            const bool taken = id == bid || (R == 1 && id == sid[0]);
+            if (!taken && snk[K - 1] > b2) {
+              b2 = snk[K - 1];
+              id2 = id;
+              e2x = cdx[K - 1];
+              e2y = cdy[K - 1];
+              beta2 = cb[K - 1];
+            }
+          });
+          const int w2 = group_argmax_lane<G>(b2, id2 >= 0, i);
+          const int src = gbase + (w2 < 0 ? 0 : w2);
+          id2 = w2 < 0 ? -1 : __shfl(id2, src, 64);
+          e2x = __shfl(e2x, src, 64);
+          e2y = __shfl(e2y, src, 64);
+          beta2 = __shfl(beta2, src, 64);
+          const bool flip2 = w2 != (id2 >> 4);
+          sx[R] = flip2 ? -e2x : e2x;
+          sy[R] = flip2 ? -e2y : e2y;
+          sb[R] = beta2;
+          sid[R] = id2;
+        });
+        const int pa = bid >> 4, pb = bid & 15;
+        const int qa = sid[0] >> 4, qb = sid[0] & 15, ra = sid[1] >> 4, rb = sid[1] & 15;
+        const bool all3 = sid[0] >= 0 && sid[1] >= 0;
+        auto coef = [&](int a, int b, T dx, T dy, T &cx, T &cy) {
+          cx = i == a ? T(-2) * dx : (i == b ? T(2) * dx : T(0));
+          cy = i == a ? T(-2) * dy : (i == b ? T(2) * dy : T(0));
+        };
+        T c1x, c1y, c2x, c2y, c3x, c3y;
+        coef(pa, pb, bdx, bdy, c1x, c1y);
+        coef(qa, qb, sx[0], sy[0], c2x, c2y);
+        coef(ra, rb, sx[1], sy[1], c3x, c3y);
+        const T g11 = T(8) * (bdx * bdx + bdy * bdy);
+        const T g22 = T(8) * (sx[0] * sx[0] + sy[0] * sy[0]);
+        const T g33 = T(8) * (sx[1] * sx[1] + sy[1] * sy[1]);
+        const T g12 = gsum<G>(c1x * c2x + c1y * c2y);
+        const T g13 = gsum<G>(c1x * c3x + c1y * c3y);
+        const T g23 = gsum<G>(c2x * c3x + c2y * c3y);
+        const T h1 = gsum<G>(c1x * uhx + c1y * uhy) - bbb;
+        const T h2 = gsum<G>(c2x * uhx + c2y * uhy) - sb[0];
+        const T h3 = gsum<G>(c3x * uhx + c3y * uhy) - sb[1];
+        // Cramer's rule on the symmetric 3 x 3 system
+        const T m11 = g22 * g33 - g23 * g23, m12 = g12 * g33 - g23 * g13, m13 = g12 * g23 - g22 * g13;
+        const T det = g11 * m11 - g12 * m12 + g13 * m13;
+        const T idet = qdiv(T(1), det);
+        const T l1 = (h1 * m11 - g12 * (h2 * g33 - g23 * h3) + g13 * (h2 * g23 - g22 * h3)) * idet;
+        const T l2 = (g11 * (h2 * g33 - g23 * h3) - h1 * m12 + g13 * (g12 * h3 - h2 * g13)) * idet;
+        const T l3 = (g11 * (g22 * h3 - h2 * g23) - g12 * (g12 * h3 - h2 * g13) + h1 * m13) * idet;
+        bool ok3 = all3 && det > T(1e-6) * g11 * g22 * g33 && l1 >= T(0) && l2 >= T(0) && l3 >= T(0);
+        const bool mv = i == pa || i == pb || i == qa || i == qb || i == ra || i == rb;
+        const T vx = uhx - l1 * c1x - l2 * c2x - l3 * c3x;
+        const T vy = uhy - l1 * c1y - l2 * c2y - l3 * c3y;
+        const bool outb = on && mv && (vx < lox || vx > hix || vy < loy || vy > hiy);
+        ok3 = ok3 && !group_any<G>(outb, lane);
+        const T wx = (on && mv) ? vx : ux, wy = (on && mv) ? vy : uy;  // unmoved: u0
+        float2 *xw = reinterpret_cast<float2 *>(sh) + 2 * G;
+        xw[i] = make_float2(wx, wy);
+        wave_lds_fence();
+        bool bad3 = !ok3;
+        static_for<1, KH + 1>([&](auto kc) {
+          constexpr int K = decltype(kc)::value;
+          const float2 v = xw[(i + K) & (G - 1)];
+          const int id = cpid[K - 1];
+          const T sn = (T(2) * (cdx[K - 1] * (v.x - wx) + cdy[K - 1] * (v.y - wy)) - cb[K - 1]) *
+                       crn[K - 1];
+          bad3 = bad3 | ((id >= 0) & (id != bid) & (id != sid[0]) & (id != sid[1]) &
+                         (sn > C.tol_add));
+        });
+        const bool accept3 = !group_any<G>(bad3, lane);
+        if (accept3) {
+          ux = wx;
+          uy = wy;
+          fq = 3;
+          fpa = pa; fpb = pb; fl1 = l1;
+          fqa = qa; fqb = qb; fl2 = l2;
+          fra = ra; frb = rb; fl3 = l3;
+          info.stage = kStShared;
+          info.iters = 3;
+          run_gi = false;
+        }
+      }
     } else if (nv <= 2) {
       // the other violated row, if any
       T b2 = thr, e2x = T(0), e2y = T(0), beta2 = T(0);
@@ -1236,15 +1334,20 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
       bool accept = !group_any<G>(bad, lane);
       bool seeded = !accept && !two && ok;
       bool second = false;  // accepted on the second guess below
-      int sqa = qa, sqb = qb;
-      if constexpr (kLdsX) {
+      bool lone = false;    // accepted with the violated row alone
+      int sqa = qa, sqb = qb, spa = pa, spb = pb;
+      if constexpr (kGuess) {
         // A rejected one-row guess violates some row r, which shares a robot
         // with p (only p's robots moved). Second guess: p and r both active
         // with no bound binding, from their 2 x 2 Gram system, accepted by
         // the checks of the shared-robot stage (wave-uniform branch: only
-        // wavefronts with such a group pay for it). The guess's commands are
-        // still in the exchange (xv).
+        // wavefronts with such a group pay for it). The guess's commands go
+        // through the group's LDS exchange (xv).
         if (__ballot(seeded) != 0) {
+          if constexpr (!kLdsX) {  // the guess's commands into the exchange
+            xv[i] = make_float2(nux, nuy);
+            wave_lds_fence();
+          }
           T rbest = C.tol_add, rdx = T(0), rdy = T(0), rbb = T(0);
           int rid = -1;
           static_for<1, KH + 1>([&](auto kc) {
@@ -1316,6 +1419,39 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
             accept = true;
             seeded = false;
           }
+          // p's multiplier came out negative: r alone, projected with every
+          // coordinate free, p then checked like every other row
+          const bool try3 = try2 && !second && m1 < T(0);
+          if (__ballot(try3) != 0) {
+            const T lr = qdiv(h2, g22);
+            const bool mv3 = i == ra || i == rb;
+            const T v3x = uhx - lr * c2x, v3y = uhy - lr * c2y;
+            const bool outb3 = on && mv3 && (v3x < lox || v3x > hix || v3y < loy || v3y > hiy);
+            const bool ok3 = try3 && lr > T(0) && !group_any<G>(outb3, lane);
+            const T w3x = (on && mv3) ? v3x : ux, w3y = (on && mv3) ? v3y : uy;
+            float2 *x3 = xw + G;  // past the second guess's exchange
+            x3[i] = make_float2(w3x, w3y);
+            wave_lds_fence();
+            bool bad3 = !ok3;
+            static_for<1, KH + 1>([&](auto kc) {
+              constexpr int K = decltype(kc)::value;
+              const float2 v = x3[(i + K) & (G - 1)];
+              const int id = cpid[K - 1];
+              const T sn = (T(2) * (cdx[K - 1] * (v.x - w3x) + cdy[K - 1] * (v.y - w3y)) - cb[K - 1]) *
+                           crn[K - 1];
+              bad3 = bad3 | ((id >= 0) & (id != rid) & (sn > C.tol_add));
+            });
+            lone = try3 && !group_any<G>(bad3, lane);
+            if (lone) {
+              nux = w3x;
+              nuy = w3y;
+              lam1 = lr;
+              spa = ra;
+              spb = rb;
+              accept = true;
+              seeded = false;
+            }
+          }
         }
       }
       // accepted: the guess is the solution; one rejected row with ok: start
@@ -1325,7 +1461,7 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
       fq = accept ? ((two || second) ? 2 : 1) : fq;
       info.stage = (two || second) ? ((shared || second) ? kStShared : kStTwoRows) : kStOneRow;
       seed = seeded;
-      fpa = pa; fpb = pb; fl1 = lam1; fdx = bdx; fdy = bdy;
+      fpa = spa; fpb = spb; fl1 = lam1; fdx = bdx; fdy = bdy;
       fqa = sqa; fqb = sqb; fl2 = lam2;
       run_gi = !accept;
       info.iters = (two || second) ? 2 : 1;
@@ -1369,8 +1505,11 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
     act_out->sa[1] = fq > 1 ? fqa : -1;
     act_out->sb[1] = fq > 1 ? fqb : -1;
     act_out->slam[1] = fq > 1 ? fl2 : T(0);
+    act_out->sa[2] = fq > 2 ? fra : -1;
+    act_out->sb[2] = fq > 2 ? frb : -1;
+    act_out->slam[2] = fq > 2 ? fl3 : T(0);
 #pragma unroll
-    for (int a = 2; a < kQR; ++a) {
+    for (int a = 3; a < kQR; ++a) {
       act_out->sa[a] = -1;
       act_out->sb[a] = -1;
       act_out->slam[a] = T(0);
