@@ -285,6 +285,9 @@ template <typename T> struct ConstRef {
 };
 // `offset` = offsetof(kernel argument struct, its SimConst member); the
 // struct must be the kernel's first parameter.
+// Only in a kernel's own body: in a device function that the compiler keeps
+// out of line, the kernel-argument segment pointer reads as null. Callees
+// take the ConstRef their kernel formed.
 template <typename T> __device__ __forceinline__ ConstRef<T> kernarg_const(size_t offset) {
   return ConstRef<T>{(uint64_t)__builtin_amdgcn_kernarg_segment_ptr() + offset};
 }

@@ -25,8 +25,11 @@ constexpr int kMaxWaveLds =
     std::max(std::max(qp_bytes_per_wave<2>(), qp_bytes_per_wave<4>()),
              std::max(qp_bytes_per_wave<8>(), qp_bytes_per_wave<16>()));
 
+// K: the launch's simulation constants in the kernel-argument segment, formed
+// by the kernel (the segment pointer is only defined in a kernel's own body).
 template <int G, bool PP>
-__device__ void run_tile(const RunArgs &A, char *wave_lds, int lane, int first, int count) {
+__device__ __forceinline__ void run_tile(const RunArgs &A, ConstRef<float> K, char *wave_lds,
+                                         int lane, int first, int count) {
   QPScratch<float, G> *sh = reinterpret_cast<QPScratch<float, G> *>(wave_lds) + lane / G;
   const int i = lane & (G - 1);
   const int grp = lane / G;
@@ -37,7 +40,6 @@ __device__ void run_tile(const RunArgs &A, char *wave_lds, int lane, int first, 
   const size_t r = (size_t)A.offset[e] + (on ? i : 0);
   const uint32_t env_id = A.env_ids ? A.env_ids[e] : A.env_base + (uint32_t)e;
   const int qp_cap = A.qp_iters[N];
-  const ConstRef<float> K = kernarg_const<float>(offsetof(RunArgs, C));
 
   float x = 0.f, y = 0.f, th = 0.f, gx = 0.f, gy = 0.f;
   int step = A.step[e], episode = A.episode[e];
@@ -96,11 +98,12 @@ __global__ __launch_bounds__(256) void k_env_run(RunArgs A) {
   if (A.num_tiles_dev && tile >= *A.num_tiles_dev) return;
   const int4 td = A.tiles[tile];
   char *mine = lds + (size_t)wave * kMaxWaveLds;
+  const ConstRef<float> K = kernarg_const<float>(offsetof(RunArgs, C));
   switch (td.x) {
-    case 2: run_tile<2, PP>(A, mine, lane, td.y, td.z); break;
-    case 4: run_tile<4, PP>(A, mine, lane, td.y, td.z); break;
-    case 8: run_tile<8, PP>(A, mine, lane, td.y, td.z); break;
-    default: run_tile<16, PP>(A, mine, lane, td.y, td.z); break;
+    case 2: run_tile<2, PP>(A, K, mine, lane, td.y, td.z); break;
+    case 4: run_tile<4, PP>(A, K, mine, lane, td.y, td.z); break;
+    case 8: run_tile<8, PP>(A, K, mine, lane, td.y, td.z); break;
+    default: run_tile<16, PP>(A, K, mine, lane, td.y, td.z); break;
   }
 }
 
