@@ -175,6 +175,10 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
   __builtin_amdgcn_s_waitcnt(0);
 
   float *obs_w = obs_lds[wave];
+  // the compile-time-count path stages bf16 rows of DB values (same buffer)
+  __bf16 *obs_b = reinterpret_cast<__bf16 *>(obs_w);
+  constexpr int DB = ((2 * NC + 4 + 7) / 8) * 8;
+  static_assert(NC == 0 || 64 * DB + 8 <= 64 * 32 * 2, "bf16 staging fits");
   // Zero the wavefront's staging area once: the MLP reads eight features per
   // lane from packed rows without bounds tests, so what it reads past the
   // last row (multiplied by zero weights, or feeding columns of robots that
@@ -222,10 +226,19 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
       rw[DC - 2] = gx - x;
       rw[DC - 1] = gy - y;
       if (on) {
-        float4 *o4 = reinterpret_cast<float4 *>(obs_w + row * DC);
+        // MLP staging in bf16 (the MLP's input precision, rounded as it would
+        // round them), rows of DB values padded with zeros
+        bf16x8 *o8 = reinterpret_cast<bf16x8 *>(obs_b + row * DB);
 #pragma unroll
-        for (int q = 0; q < DC / 4; ++q)
-          o4[q] = make_float4(rw[4 * q], rw[4 * q + 1], rw[4 * q + 2], rw[4 * q + 3]);
+        for (int q = 0; q < DB / 8; ++q) {
+          floatx4 lo4, hi4;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            lo4[j] = 8 * q + j < DC ? rw[(8 * q + j) % DC] : 0.f;
+            hi4[j] = 8 * q + 4 + j < DC ? rw[(8 * q + 4 + j) % DC] : 0.f;
+          }
+          o8[q] = pack_bf16x8<false>(lo4, hi4);
+        }
         if (A.obs) {
           float4 *g4 = reinterpret_cast<float4 *>(A.obs + ((size_t)t * A.E + e0) * (size_t)(NC * DC)) +
                        row * (DC / 4);
@@ -283,7 +296,9 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
       // rows whose logits are never used
       const float *src = obs_w + (ng * N + ni) * D + 8 * g;
       bf16x8 xb;
-      if ((D & 3) == 0) {
+      if constexpr (NC > 0 && ((2 * NC + 4) & 3) == 0) {
+        xb = *reinterpret_cast<const bf16x8 *>(obs_b + (ng * NC + ni) * DB + 8 * g);
+      } else if ((D & 3) == 0) {
         const float4 f0 = reinterpret_cast<const float4 *>(src)[0];
         const float4 f1 = reinterpret_cast<const float4 *>(src)[1];
         xb = pack_bf16x8<false>((floatx4){f0.x, f0.y, f0.z, f0.w},
