@@ -141,3 +141,41 @@ def test_noalloc_rejects_more_envs_than_the_array_holds():
     counts = torch.full((E,), 2, dtype=torch.int32, device="cuda")
     with pytest.raises(RuntimeError, match="65536"):
         R.env_run_noalloc(ctx, R.params(), counts, b, 1)
+
+
+def test_noalloc_under_graph_capture():
+    """The call can be captured in a HIP graph (nothing to allocate, no memset
+    node): three replays, with eager work and synchronisations in between,
+    each equal bit for bit to an eager call from the same state."""
+    import torch
+
+    R, ctx = ctx_and_lib()
+    counts = _counts(41, 517)
+    plan, b, _ = _state_pair(R, ctx, counts, seed=6, env_id_base=2)
+    p = R.params(seed=6)
+    counts_dev = torch.from_numpy(np.asarray(counts, np.int32)).cuda()
+    rsum = torch.zeros(len(counts), device="cuda")
+    bad = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    banner("env_run_noalloc graph capture")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        R.env_run_noalloc(ctx, p, counts_dev, b, 6, t_global0=900, reward_sum=rsum, bad_envs=bad,
+                          stream=side)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        c = R.Batch(*(t.clone() for t in (b.x, b.y, b.theta, b.goal_x, b.goal_y, b.step,
+                                          b.episode)), 0, 2)
+        csum = rsum.clone()
+        graph.replay()
+        torch.cuda.synchronize()
+        R.env_run_noalloc(ctx, p, counts_dev, c, 6, t_global0=900, reward_sum=csum)
+        torch.cuda.synchronize()
+        assert int(host(bad)[0]) == 0
+        for name in ("x", "y", "theta", "goal_x", "goal_y", "step", "episode"):
+            np.testing.assert_array_equal(host(getattr(b, name)), host(getattr(c, name)),
+                                          err_msg=f"replay {rep}: {name}")
+        np.testing.assert_array_equal(host(rsum), host(csum))
+        _ = (torch.ones(1000, device="cuda") * rep).sum().item()  # eager work between replays
+    plan.close()
