@@ -253,7 +253,7 @@ def serving(R, ctx, seed=0, count=2000, skip=200, budget=64 << 30, stress_budget
                 if info is None:
                     break
                 # completion - arrival: server clock from submission to
-                # completion plus the driver's own delay in submitting
+                # completion plus the load generator's own delay in submitting
                 lat[info.id] = (info.finish_time - info.submit_time) + late[info.id]
             if not busy and k < count:
                 time.sleep(max(0.0, min(1e-3, reqs[k]["arrival"] - (time.perf_counter() - start))))

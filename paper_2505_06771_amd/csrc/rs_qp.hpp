@@ -1015,6 +1015,12 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
   //  * Two rows through a shared robot: assuming no bound binds on the three
   //    robots, the multipliers solve the 2 x 2 Gram system; the guess also
   //    needs both multipliers >= 0 and the three commands inside their bounds.
+  //  * FP32 only: after a rejected one-row guess, rows p and r (the row that
+  //    guess violates) both active, or r alone when p's multiplier comes out
+  //    negative; and for exactly three violated rows, all three active. Each
+  //    solves its rows' Gram system with no bound binding and is accepted
+  //    when the multipliers are >= 0, the moved robots stay inside their
+  //    boxes and every other row holds: the KKT conditions of the QP.
   // A rejected one-row guess (with p active and the clipped coordinates fixed)
   // is a dual-feasible start for the active-set loop below; otherwise the loop
   // starts from u0.
