@@ -433,6 +433,13 @@ rs_status rs_autotune(rs_ctx *ctx, const rs_params *p, const int32_t *robots, in
 rs_status rs_autotune_batch(rs_ctx *ctx, const rs_params *p, const rs_plan *plan,
                             const rs_batch *b, int32_t steps, double tol, rs_schedule *out);
 rs_status rs_get_schedule(rs_ctx *ctx, rs_schedule *out);
+/* Sets the context's schedule (used by plans created afterwards with schedule
+ * NULL, by env_run_noalloc and by the server), e.g. one an earlier
+ * rs_autotune returned. Checked on the host: block_threads 0 or a multiple of
+ * 64 up to 256; per robot count n = 2..16, lanes_per_env[n] 0 or a power of
+ * two in n..16, envs_per_wave[n] 0..64/lanes, qp_iters[n] >= 0;
+ * RS_ERR_INVALID_ARG otherwise, the schedule left unchanged. */
+rs_status rs_set_schedule(rs_ctx *ctx, const rs_schedule *s);
 
 /* ---------------------------------------------------------------------------
  * Serving loop (continuous batching of rollout requests).

@@ -386,6 +386,23 @@ rs_status rs_get_schedule(rs_ctx *ctx, rs_schedule *out) {
   return RS_OK;
 }
 
+rs_status rs_set_schedule(rs_ctx *ctx, const rs_schedule *sc) {
+  RS_CHECK_ARG(ctx != nullptr && sc != nullptr, "ctx/schedule is NULL");
+  RS_CHECK_ARG(sc->block_threads >= 0 && sc->block_threads <= 256 && sc->block_threads % 64 == 0,
+               "block_threads %d: 0 or a multiple of 64 up to 256", sc->block_threads);
+  for (int n = 2; n <= RS_MAX_ROBOTS; ++n) {
+    const int g = sc->lanes_per_env[n];
+    RS_CHECK_ARG(g == 0 || (g >= n && g <= RS_MAX_ROBOTS && (g & (g - 1)) == 0),
+                 "lanes_per_env[%d] = %d: 0 or a power of two in %d..16", n, g, n);
+    const int lanes = g ? g : pow2_group(n);
+    RS_CHECK_ARG(sc->envs_per_wave[n] >= 0 && sc->envs_per_wave[n] <= 64 / lanes,
+                 "envs_per_wave[%d] = %d: 0..%d", n, sc->envs_per_wave[n], 64 / lanes);
+    RS_CHECK_ARG(sc->qp_iters[n] >= 0, "qp_iters[%d] = %d < 0", n, sc->qp_iters[n]);
+  }
+  ctx->sched = *sc;
+  return RS_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Autotuner
 // ---------------------------------------------------------------------------

@@ -142,6 +142,7 @@ def lib():
                                   _VP, _VP, _VP, _VP, _VP, _VP]),
         "rs_autotune": (i32, [_VP, P(RsParams), _VP, i32, i32, i32, dbl, P(RsSchedule)]),
         "rs_get_schedule": (i32, [_VP, P(RsSchedule)]),
+        "rs_set_schedule": (i32, [_VP, P(RsSchedule)]),
         "rs_autotune_batch": (i32, [_VP, P(RsParams), _VP, P(RsBatch), i32, dbl, P(RsSchedule)]),
         "rs_server_create": (i32, [_VP, P(RsParams), i64, i32, P(_VP)]),
         "rs_server_destroy": (i32, [_VP]),
@@ -417,6 +418,17 @@ def autotune(ctx: Context, p: RsParams, robots, envs: int = 4096, steps: int = 5
     out = RsSchedule()
     _check(lib().rs_autotune(ctx.handle, ctypes.byref(p), arr.ctypes.data, arr.size, envs, steps,
                              tol, ctypes.byref(out)))
+    return out
+
+
+def set_schedule(ctx: Context, schedule: RsSchedule):
+    """Set the context's schedule (plans made afterwards, env_run_noalloc, server)."""
+    _check(lib().rs_set_schedule(ctx.handle, ctypes.byref(schedule)))
+
+
+def get_schedule(ctx: Context) -> RsSchedule:
+    out = RsSchedule()
+    _check(lib().rs_get_schedule(ctx.handle, ctypes.byref(out)))
     return out
 
 

@@ -203,3 +203,12 @@ def test_binding_argument_counts_match_the_header(R):
         assert len(fn.argtypes) == n, f"{name}: binding {len(fn.argtypes)} args, header {n}"
         checked += 1
     assert checked >= 25
+
+
+def test_set_schedule_validates_on_the_host(R):
+    """rs_set_schedule refuses malformed schedules before touching the
+    context (no device work: a NULL context is refused first)."""
+    L = R.lib()
+    s = R.RsSchedule()
+    assert L.rs_set_schedule(None, ctypes.byref(s)) == 1
+    assert b"NULL" in L.rs_last_error()

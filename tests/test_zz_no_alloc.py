@@ -179,3 +179,31 @@ def test_noalloc_under_graph_capture():
         np.testing.assert_array_equal(host(rsum), host(csum))
         _ = (torch.ones(1000, device="cuda") * rep).sum().item()  # eager work between replays
     plan.close()
+
+
+def test_noalloc_equals_env_run_under_a_set_schedule():
+    """A schedule with doubled lane groups, partial tiles and a wide
+    iteration cap (rs_set_schedule): the device-built work list runs the same
+    tiles' arithmetic as a plan made from that schedule, bit for bit; bad
+    schedules are refused and leave the context's schedule as it was."""
+    R, ctx = ctx_and_lib()
+    before = R.get_schedule(ctx)
+    s = R.RsSchedule()
+    s.block_threads = 128
+    for n in range(2, 17):
+        g = 2 if n <= 2 else 4 if n <= 4 else 8 if n <= 8 else 16
+        s.lanes_per_env[n] = min(16, 2 * g) if n % 2 == 0 else g
+        s.envs_per_wave[n] = max(1, 64 // s.lanes_per_env[n] // (2 + n % 3))
+        s.qp_iters[n] = 8 * n + 40
+    bad = R.RsSchedule()
+    bad.lanes_per_env[9] = 8  # fewer lanes than robots
+    with pytest.raises(RuntimeError, match="lanes_per_env"):
+        R.set_schedule(ctx, bad)
+    assert R.get_schedule(ctx).block_threads == before.block_threads
+    R.set_schedule(ctx, s)
+    try:
+        banner("env_run_noalloc under a set schedule")
+        _compare(R, ctx, _counts(51, 2049), seed=12, steps=8, budgets=True)
+        _compare(R, ctx, _counts(52, 200), seed=13, steps=8, controller=2, action_noise=0.05)
+    finally:
+        R.set_schedule(ctx, before)
