@@ -270,7 +270,7 @@ rs_status barrier_certificate(rs_ctx *ctx, const rs_params *p, int32_t num_envs,
 
 /* ---------------------------------------------------------------------------
  * rollout -- `horizon` fused policy steps in one persistent launch (FP32 state,
- * RS_CTRL_DISCRETE or RS_CTRL_WAYPOINT, action noise and scenario as set).
+ * RS_CTRL_DISCRETE, RS_CTRL_WAYPOINT or RS_CTRL_POSE, action noise and scenario as set).
  * For t = 0..H-1:
  * obs_t of the current state; logits = MLP(bf16(obs_t)) with bf16 weights
  * and activations and FP32 accumulation;
@@ -351,7 +351,7 @@ rs_status env_reset_mixed(rs_ctx *ctx, const rs_params *p, const rs_plan *plan,
 
 /* ---------------------------------------------------------------------------
  * env_run -- `steps` consecutive env_step calls with drawn actions for a mixed
- * batch in ONE persistent launch (FP32; RS_CTRL_DISCRETE or RS_CTRL_WAYPOINT,
+ * batch in ONE persistent launch (FP32; RS_CTRL_DISCRETE, RS_CTRL_WAYPOINT or RS_CTRL_POSE,
  * action noise and scenario as set). Env e runs
  * steps_per_env ? min(steps, steps_per_env[e]) : steps steps, with stream time
  * t_start[e] + k (t_start NULL: t_global0 + k) at its k-th step. Outputs (each

@@ -215,7 +215,7 @@ static rs_status check_mixed(const rs_ctx *ctx, const rs_params *p, const rs_pla
   rs_status s = check_params(p);
   if (s != RS_OK) return s;
   RS_CHECK_ARG(p->dtype == RS_F32, "mixed batches run in FP32");
-  RS_CHECK_ARG(action_driven(p->controller), "env_run draws actions: discrete or waypoint controller");
+  RS_CHECK_ARG(action_driven(p->controller), "env_run draws actions: discrete, waypoint or pose controller");
   RS_CHECK_ARG(b->num_envs == plan->num_envs, "batch has %d envs, plan %d", b->num_envs,
                plan->num_envs);
   RS_CHECK_ARG(b->x && b->y && b->theta && b->goal_x && b->goal_y && b->step && b->episode,

@@ -466,7 +466,7 @@ extern "C" rs_status rollout(rs_ctx *ctx, const rs_params *p, const rs_batch *b,
   if (s != RS_OK) return s;
   RS_CHECK_ARG(b != nullptr && policy != nullptr, "batch/policy is NULL");
   RS_CHECK_ARG(p->dtype == RS_F32, "rollout runs in FP32 (dtype must be RS_F32)");
-  RS_CHECK_ARG(action_driven(p->controller), "rollout samples actions: discrete or waypoint controller");
+  RS_CHECK_ARG(action_driven(p->controller), "rollout samples actions: discrete, waypoint or pose controller");
   RS_CHECK_ARG(b->num_envs >= 1, "num_envs must be >= 1");
   RS_CHECK_ARG((int64_t)b->num_envs * b->robots < (int64_t)1 << 31, "num_envs * robots must be < 2^31");
   RS_CHECK_ARG(b->robots >= 2 && 2 * b->robots + 4 <= 32,
