@@ -201,9 +201,10 @@ __device__ __forceinline__ void wave_lds_fence() {
 
 // Phase clock of a wavefront (diagnostic builds only). Built with
 // -DRS_PHASE_TIMERS, the fused rollout reads the shader clock at the
-// boundaries of its step phases and sums the cycles of each phase per
-// wavefront (wavefront-uniform, in scalar registers); without the flag every
-// call here compiles to nothing.
+// boundaries of its step phases and adds the cycles of each phase to the
+// wavefront's counters in LDS (one 64-bit add by the first active lane, so
+// the counters take no registers from the step loop and a mark inside a
+// branch still counts); without the flag every call here compiles to nothing.
 enum : int {
   kPhObs = 0,     // observation rows: assembly, LDS staging, HBM stores
   kPhMlp = 1,     // policy MLP on MFMA
@@ -218,22 +219,33 @@ enum : int {
 struct PhaseClock {
 #ifdef RS_PHASE_TIMERS
   uint64_t last;
-  uint64_t acc[kPhases];
-  __device__ __forceinline__ void start() {
-#pragma unroll
-    for (int k = 0; k < kPhases; ++k) acc[k] = 0;
+  unsigned long long *acc;  // the wavefront's kPhases counters in LDS
+  int lane;
+  __device__ __forceinline__ void start(unsigned long long *lds_acc, int lane_id) {
+    acc = lds_acc;
+    lane = lane_id;
+    if (lane < kPhases) acc[lane] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     last = __builtin_amdgcn_s_memtime();
+  }
+  __device__ __forceinline__ void add(int k, unsigned long long v) {
+    if (lane == __builtin_amdgcn_readfirstlane(lane))
+      __hip_atomic_fetch_add(acc + k, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
   }
   __device__ __forceinline__ void mark(int k) {
     const uint64_t now = __builtin_amdgcn_s_memtime();
-    acc[k] += now - last;
+    add(k, now - last);
     last = now;
   }
-  __device__ __forceinline__ void count(int k, bool any) { acc[k] += any ? 1u : 0u; }
+  __device__ __forceinline__ void count(int k, bool any) {
+    if (any) add(k, 1ull);
+  }
   __device__ __forceinline__ uint64_t last_or_zero() const { return last; }
 #else
   __device__ __forceinline__ uint64_t last_or_zero() const { return 0; }
-  __device__ __forceinline__ void start() {}
+  __device__ __forceinline__ void start(unsigned long long *, int) {}
   __device__ __forceinline__ void mark(int) {}
   __device__ __forceinline__ void count(int, bool) {}
 #endif

@@ -196,7 +196,12 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
 
   uint4 qblk = make_uint4(0u, 0u, 0u, 0u);  // this lane's Philox block (G >= 4)
   PhaseClock pc;
-  pc.start();
+#ifdef RS_PHASE_TIMERS
+  __shared__ unsigned long long phase_lds[kRollWaves][kPhases];
+  pc.start(phase_lds[wave], lane);
+#else
+  pc.start(nullptr, lane);
+#endif
   const uint64_t t_begin = pc.last_or_zero();
   for (int t = 0; t < A.H; ++t) {
     // ---- 1. observation -> LDS (packed) -> HBM --------------------------
@@ -415,14 +420,10 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
   if (on) { A.x[r] = x; A.y[r] = y; A.th[r] = th; A.gx[r] = gx; A.gy[r] = gy; }
   if (env_ok && i == 0) { A.step[e] = step; A.episode[e] = episode; }
 #ifdef RS_PHASE_TIMERS
-  pc.acc[kPhTotal] = pc.last - t_begin;
+  pc.add(kPhTotal, pc.last - t_begin);
+  wave_lds_sync();
   const int wid = blockIdx.x * kRollWaves + wave;
-  if (lane < kPhases && wid < kTimedWaves) {
-    unsigned long long v = 0;
-#pragma unroll
-    for (int k = 0; k < kPhases; ++k) v = lane == k ? pc.acc[k] : v;
-    rs_phase_cycles_dev[wid][lane] = v;
-  }
+  if (lane < kPhases && wid < kTimedWaves) rs_phase_cycles_dev[wid][lane] = phase_lds[wave][lane];
 #else
   (void)t_begin;
 #endif
