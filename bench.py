@@ -47,12 +47,17 @@ def rollout_algorithmic_bytes(E, N, H):
 
 
 def kernel_source_hash():
+    """First 16 hex digits of the sha256 of the kernel sources and of the
+    build script that holds their compiler flags."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2505_06771_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode())
             h.update(f.read())
+    with open(os.path.join(ROOT, "paper_2505_06771_amd", "build.py"), "rb") as f:
+        h.update(b"build.py")
+        h.update(f.read())
     return h.hexdigest()[:16]
 
 
