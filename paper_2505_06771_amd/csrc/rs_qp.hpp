@@ -658,7 +658,50 @@ __device__ __noinline__ QPLoopOut<T> qp_active_set(QPScratch<T, G> *sh, int lane
     }
   }
   bool go = run_gi && !dead;
+  [[maybe_unused]] bool first = true;  // FP32: the first pick may take the caller's row
   while (go) {
+    if constexpr (std::is_same<T, float>::value) {
+      // FP32: the caller hands over the row its closed-form stages found most
+      // violated at this start: with a seed, through the group's scratch
+      // (L[0..3]: row id a << 4 | b, D = p_a - p_b, b); without one, the rows
+      // of a rejected one- or two-row guess start at u0, where their first
+      // row (fpa, fpb, fdx, fdy) is the most violated one, its b from the
+      // same formula as the geometry above. It enters without a scan once its
+      // violation here is confirmed; otherwise (or with no row handed over)
+      // the first pick scans as usual.
+      if (first) {
+        first = false;
+        int pid = fpa >= 0 ? (fpa << 4 | fpb) : -1;
+        T rdx = fdx, rdy = fdy;
+        const T rd2 = fdx * fdx + fdy * fdy;
+        const T rh = rd2 - C.rs2;
+        T rb = C.gamma * (rh * rh * rh);
+        if (seed) {
+          const float4 pr = reinterpret_cast<const float4 *>(sh->L)[0];
+          pid = __float_as_int(pr.x);
+          rdx = pr.y;
+          rdy = pr.z;
+          rb = pr.w;
+        }
+        const int ea = pid >> 4, eb = pid & 15;
+        const T sgn = i == ea ? T(-2) : (i == eb ? T(2) : T(0));
+        const T ex = on ? sgn * rdx : T(0), ey = on ? sgn * rdy : T(0);
+        const T v0 = gsum<G>(ex * ux + ey * uy) - rb;
+        if (pid >= 0 && v0 > T(0)) {
+          if (++info.iters > cap) { info.status = 2; break; }
+          p_pair = true;
+          pa = ea;
+          pb = eb;
+          pk = 0;
+          psig = 0;
+          cpx = ex;
+          cpy = ey;
+          bp = rb;
+          lam_p = T(0);
+          pend = true;
+        }
+      }
+    }
     if (!pend) {
       // --- most violated constraint (argmax carries the row's data) --------
       T best = C.tol_add, bdx = T(0), bdy = T(0), bbb = T(0);
@@ -1379,6 +1422,10 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
           const bool flipr = wr != (rid >> 4);
           rdx = flipr ? -rdx : rdx;
           rdy = flipr ? -rdy : rdy;
+          // a seeded loop starts at this guess, where r is the most violated
+          // row: handed over through the group's scratch (L[0..3])
+          if (seeded && i == 0)
+            reinterpret_cast<float4 *>(sh->L)[0] = make_float4(__int_as_float(rid), rdx, rdy, rbb);
           const int ra = rid >> 4, rb = rid & 15;
           const bool try2 =
               seeded && rid >= 0 && (ra == pa || ra == pb || rb == pa || rb == pb);
