@@ -1070,25 +1070,64 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
   bool run_gi = !dead;
   if (!dead) {
     const T thr = C.tol_add;
-    T best = thr, bdx = T(0), bdy = T(0), bbb = T(0);
-    int bid = -1, nviol = 0;
-    static_for<1, KH + 1>([&](auto kc) {
-      constexpr int K = decltype(kc)::value;
-      nviol += snk[K - 1] > thr ? 1 : 0;
-      if (snk[K - 1] > best) {
-        best = snk[K - 1];
-        bid = cpid[K - 1];
-        bdx = cdx[K - 1];
-        bdy = cdy[K - 1];
-        bbb = cb[K - 1];
-      }
-    });
-    // most violated row of the group: winner lane by one integer butterfly,
-    // its row's data read from that lane
     const int gbase = lane & ~(G - 1);
-    const int wl = group_argmax_lane<G>(best, bid >= 0, i);
-    const int nv = gsum<G>(nviol);
-    {
+    T bdx = T(0), bdy = T(0), bbb = T(0);
+    int bid = -1, nv = 0;
+    if constexpr (kGuess) {
+      // FP32: most violated row of the group by one integer key per row (the
+      // score's float bits truncated by a byte, 255 - row id in the low byte:
+      // a positive float orders like its bits), the maximum over the owned
+      // rows, then over the group by one butterfly. The winner does not depend
+      // on which lane owns which row, so it is the same for every group width.
+      // Its D and b are recomputed from the two robots' projection points, by
+      // the formulas of the scan (the same values the owner holds).
+      uint32_t bkey = 0u;
+      int nviol = 0;
+      static_for<1, KH + 1>([&](auto kc) {
+        constexpr int K = decltype(kc)::value;
+        const bool v = snk[K - 1] > thr;
+        nviol += v ? 1 : 0;
+        const uint32_t k =
+            v ? ((__float_as_uint((float)snk[K - 1]) & 0xFFFFFF00u) | (uint32_t)(255 - cpid[K - 1]))
+              : 0u;
+        bkey = k > bkey ? k : bkey;
+      });
+      const int key =
+          gred<G>((int)bkey, [](int a, int b) { return (uint32_t)a > (uint32_t)b ? a : b; });
+      nv = gsum<G>(nviol);
+      bid = key == 0 ? -1 : 255 - (key & 255);
+      const int ra = bid < 0 ? 0 : bid >> 4, rb = bid < 0 ? 0 : bid & 15;
+      T pax, pay, pbx, pby;
+      if constexpr (kLdsX) {
+        const float4 va = xq[ra], vb = xq[rb];
+        pax = va.x; pay = va.y; pbx = vb.x; pby = vb.y;
+      } else {
+        pax = __shfl(px, gbase + ra, 64); pay = __shfl(py, gbase + ra, 64);
+        pbx = __shfl(px, gbase + rb, 64); pby = __shfl(py, gbase + rb, 64);
+      }
+      bdx = pax - pbx;
+      bdy = pay - pby;
+      const T d2 = bdx * bdx + bdy * bdy;
+      const T h = d2 - C.rs2;
+      bbb = C.gamma * (h * h * h);
+    } else {
+      T best = thr;
+      int nviol = 0;
+      static_for<1, KH + 1>([&](auto kc) {
+        constexpr int K = decltype(kc)::value;
+        nviol += snk[K - 1] > thr ? 1 : 0;
+        if (snk[K - 1] > best) {
+          best = snk[K - 1];
+          bid = cpid[K - 1];
+          bdx = cdx[K - 1];
+          bdy = cdy[K - 1];
+          bbb = cb[K - 1];
+        }
+      });
+      // most violated row of the group: winner lane by one integer
+      // butterfly, its row's data read from that lane
+      const int wl = group_argmax_lane<G>(best, bid >= 0, i);
+      nv = gsum<G>(nviol);
       const int src = gbase + (wl < 0 ? 0 : wl);
       bid = wl < 0 ? -1 : __shfl(bid, src, 64);
       bdx = __shfl(bdx, src, 64);
