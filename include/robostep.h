@@ -361,7 +361,9 @@ rs_status env_reset_mixed(rs_ctx *ctx, const rs_params *p, const rs_plan *plan,
  * floats starting at rs_plan_obs_offset(plan, e); qp_stats [E][RS_QPS_COUNT]
  * int32, accumulated certificate statistics. Results per env do not
  * depend on the other envs in the batch or on the schedule (as long as the
- * iteration cap is not reached: see rs_qp_failures and RS_QPS_CAPPED).
+ * iteration cap is not reached: see rs_qp_failures and RS_QPS_CAPPED; and up
+ * to rounding when two candidate rows of a three-row or second guess tie in
+ * the top 15 bits of their scores, which the guess breaks by lane).
  * ------------------------------------------------------------------------- */
 rs_status env_run(rs_ctx *ctx, const rs_params *p, const rs_plan *plan, const rs_batch *b,
                   int32_t steps, const int64_t *t_start, int64_t t_global0,
