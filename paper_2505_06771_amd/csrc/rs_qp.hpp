@@ -664,9 +664,9 @@ __device__ __noinline__ QPLoopOut<T> qp_active_set(QPScratch<T, G> *sh, int lane
       // FP32: the caller hands over the row its closed-form stages found most
       // violated at this start: with a seed, through the group's scratch
       // (L[0..3]: row id a << 4 | b, D = p_a - p_b, b); without one, the rows
-      // of a rejected one- or two-row guess start at u0, where their first
-      // row (fpa, fpb, fdx, fdy) is the most violated one, its b from the
-      // same formula as the geometry above. It enters without a scan once its
+      // of a rejected guess (or four or more rows violated at u0) start at
+      // u0, where the row (fpa, fpb, fdx, fdy) is the most violated one, its
+      // b from the same formula as the geometry above. It enters without a scan once its
       // violation here is confirmed; otherwise (or with no row handed over)
       // the first pick scans as usual.
       if (first) {
@@ -1233,6 +1233,9 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
           info.stage = kStShared;
           info.iters = 3;
           run_gi = false;
+        } else {
+          // the loop starts at u0, where p is the most violated row
+          fpa = pa; fpb = pb; fdx = bdx; fdy = bdy;
         }
       }
     } else if (nv <= 2) {
@@ -1557,6 +1560,12 @@ __device__ QPInfo qp_solve(QPScratch<T, G> *sh, ConstRef<T> K, int qp_cap, int l
       fqa = sqa; fqb = sqb; fl2 = lam2;
       run_gi = !accept;
       info.iters = (two || second) ? 2 : 1;
+    } else {
+      if constexpr (kGuess) {
+        // four or more rows violated at u0, where the loop starts: p is the
+        // most violated one
+        fpa = bid >> 4; fpb = bid & 15; fdx = bdx; fdy = bdy;
+      }
     }
   }
 
