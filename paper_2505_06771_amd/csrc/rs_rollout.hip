@@ -102,15 +102,32 @@ __device__ __forceinline__ int perm_hidden(int s, int g, int j) {
 // NC > 0 fixes the robot count at compile time (NC <= G); NC = 0 reads it
 // from the arguments. STATS: the kernel also counts the certificate's stages
 // per env (qp_stats); the kernels without it carry none of that code.
+// Teams of three (NC = 3) run three wavefronts per SIMD: at the paper's team
+// size a launch has a third more wavefronts than 8-robot envs of the same
+// robot count (one lane in four of a 4-lane group is idle), and two per SIMD
+// would leave a second, partial round. That needs at most 168 VGPRs and 53 KiB
+// of LDS per block: the policy weights stay in LDS and are read at each step's
+// MLP, the staging and logit areas are sized to what three robots use.
+template <int NC> constexpr int rollout_waves_per_simd() { return NC == 3 ? 3 : 2; }
+
 template <int G, int NC, bool PP, bool STATS>
-__global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
+__global__ __launch_bounds__(kRollBlock, rollout_waves_per_simd<NC>()) void k_rollout(RolloutArgs A) {
   constexpr int EPW = 64 / G;
+  constexpr bool kTeam3 = NC == 3;
+  // staging floats per wavefront: 3-robot rows are 10 floats, and the MLP
+  // reads up to 22 floats past the last one (zero weights)
+  constexpr int kObsFloats = kTeam3 ? 704 : 64 * 32;
+  constexpr int kLogitRows = kTeam3 ? 2 : 4;
+  // teams of three: the MFMA A-operand fragments of the three layers (14 x 64
+  // bf16x8) after the wavefronts' staging areas
+  constexpr int kWFloats = kTeam3 ? 14 * 64 * 4 : 0;
   __shared__ QPScratch<float, G> qs[kRollBlock / G];
-  __shared__ __attribute__((aligned(16))) float obs_lds[kRollWaves][64 * 32];
+  __shared__ __attribute__((aligned(16))) float obs_lds[kRollWaves * kObsFloats + kWFloats];
   // logits 4g..4g+3 of robot n at [g][n], g = 0..3 (g >= 2: the padding
   // rows of the last layer, never read; written so that the four tiles of
-  // the MLP are one branch-free block the scheduler can interleave)
-  __shared__ float4 logit_lds[kRollWaves][4 * 64];
+  // the MLP are one branch-free block the scheduler can interleave; teams of
+  // three keep only the rows that are read)
+  __shared__ float4 logit_lds[kRollWaves][kLogitRows * 64];
   // hidden-layer biases in the accumulator layout: [layer][tile][lane group]
   __shared__ float4 bias_lds[2][4][4];
 
@@ -121,6 +138,35 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
     const float *bsrc = layer ? A.b2 : A.b1;
     bias_lds[layer][mt][gg] = make_float4(bsrc[16 * mt + 4 * gg], bsrc[16 * mt + 4 * gg + 1],
                                           bsrc[16 * mt + 4 * gg + 2], bsrc[16 * mt + 4 * gg + 3]);
+  }
+  bf16x8 *wfrag = reinterpret_cast<bf16x8 *>(obs_lds + kRollWaves * kObsFloats);  // [14][64]
+  if constexpr (kTeam3) {
+    if (wave == 0) {  // the fragments are the same for every wavefront
+      const int g = lane >> 4, c16 = lane & 15;
+      const __bf16 zero = (__bf16)0.0f;
+      constexpr int Dt = 2 * NC + 4;
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) {
+        bf16x8 w1;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) w1[j] = 8 * g + j < Dt ? A.w1[(8 * g + j) * 64 + 16 * mt + c16] : zero;
+        wfrag[mt * 64 + lane] = w1;
+#pragma unroll
+        for (int sk = 0; sk < 2; ++sk) {
+          bf16x8 w2;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) w2[j] = A.w2[perm_hidden(sk, g, j) * 64 + 16 * mt + c16];
+          wfrag[(4 + 2 * mt + sk) * 64 + lane] = w2;
+        }
+      }
+#pragma unroll
+      for (int sk = 0; sk < 2; ++sk) {
+        bf16x8 w3;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) w3[j] = c16 < 5 ? A.w3[perm_hidden(sk, g, j) * 5 + c16] : zero;
+        wfrag[(12 + sk) * 64 + lane] = w3;
+      }
+    }
   }
   __syncthreads();  // the only block-wide barrier, before any wavefront leaves
   const int i = lane & (G - 1);
@@ -146,25 +192,25 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
 
   // ---- policy weights into registers (MFMA A-operand fragments) ----------
   const int g = lane >> 4, c16 = lane & 15;
-  bf16x8 w1f[4], w2f[4][2], w3f[2];
+  bf16x8 rw1f[4], rw2f[4][2], rw3f[2];  // (not for teams of three)
   floatx4 b3f;
   const __bf16 zero = (__bf16)0.0f;
 #pragma unroll
-  for (int mt = 0; mt < 4; ++mt) {
+  for (int mt = 0; mt < 4 && !kTeam3; ++mt) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int f = 8 * g + j;
-      w1f[mt][j] = f < D ? A.w1[f * 64 + 16 * mt + c16] : zero;
+      rw1f[mt][j] = f < D ? A.w1[f * 64 + 16 * mt + c16] : zero;
     }
 #pragma unroll
     for (int sk = 0; sk < 2; ++sk)
 #pragma unroll
-      for (int j = 0; j < 8; ++j) w2f[mt][sk][j] = A.w2[perm_hidden(sk, g, j) * 64 + 16 * mt + c16];
+      for (int j = 0; j < 8; ++j) rw2f[mt][sk][j] = A.w2[perm_hidden(sk, g, j) * 64 + 16 * mt + c16];
   }
 #pragma unroll
-  for (int sk = 0; sk < 2; ++sk)
+  for (int sk = 0; sk < 2 && !kTeam3; ++sk)
 #pragma unroll
-    for (int j = 0; j < 8; ++j) w3f[sk][j] = c16 < 5 ? A.w3[perm_hidden(sk, g, j) * 5 + c16] : zero;
+    for (int j = 0; j < 8; ++j) rw3f[sk][j] = c16 < 5 ? A.w3[perm_hidden(sk, g, j) * 5 + c16] : zero;
 #pragma unroll
   for (int j = 0; j < 4; ++j) b3f[j] = (4 * g + j) < 5 ? A.b3[4 * g + j] : 0.0f;
 
@@ -174,7 +220,7 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
   // stall until its observation stores had landed.
   __builtin_amdgcn_s_waitcnt(0);
 
-  float *obs_w = obs_lds[wave];
+  float *obs_w = obs_lds + wave * kObsFloats;
   // the compile-time-count path stages bf16 rows of DB values (same buffer)
   __bf16 *obs_b = reinterpret_cast<__bf16 *>(obs_w);
   constexpr int DB = ((2 * NC + 4 + 7) / 8) * 8;
@@ -183,9 +229,14 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
   // lane from packed rows without bounds tests, so what it reads past the
   // last row (multiplied by zero weights, or feeding columns of robots that
   // do not exist) must be finite.
+  if constexpr (kTeam3) {
+    for (int q = lane; q < kObsFloats / 4; q += 64)
+      reinterpret_cast<float4 *>(obs_w)[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+  } else {
 #pragma unroll
-  for (int q = 0; q < 8; ++q)
-    reinterpret_cast<float4 *>(obs_w)[q * 64 + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int q = 0; q < 8; ++q)
+      reinterpret_cast<float4 *>(obs_w)[q * 64 + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
   wave_lds_sync();
   float4 *logit_w = logit_lds[wave];
   QPScratch<float, G> *sh = &qs[threadIdx.x / G];
@@ -204,6 +255,11 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
 #endif
   const uint64_t t_begin = pc.last_or_zero();
   for (int t = 0; t < A.H; ++t) {
+    // teams of three: the lane's robot index, opaque to the compiler, so the
+    // lane masks derived from it are formed anew each step rather than held
+    // across the loop (which at 168 VGPRs would spill)
+    int il = i;
+    if constexpr (kTeam3) asm volatile("" : "+v"(il));
     // ---- 1. observation -> LDS (packed) -> HBM --------------------------
     if constexpr (NC > 0 && ((2 * NC + 4) & 3) == 0) {
       // Row assembled in registers: every lane of the group posts its (x, y)
@@ -225,8 +281,8 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
       }
 #pragma unroll
       for (int S = 0; S < NC - 1; ++S) {
-        rw[4 + 2 * S] = (S < i ? px_[S] : px_[S + 1]) - x;
-        rw[5 + 2 * S] = (S < i ? py_[S] : py_[S + 1]) - y;
+        rw[4 + 2 * S] = (S < il ? px_[S] : px_[S + 1]) - x;
+        rw[5 + 2 * S] = (S < il ? py_[S] : py_[S + 1]) - y;
       }
       rw[DC - 2] = gx - x;
       rw[DC - 1] = gy - y;
@@ -285,6 +341,29 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
     // ---- 2. policy MLP on MFMA, one tile of 16 robots at a time ----------
     // hidden biases (accumulator seeds): read once per step, shared by the
     // four tiles
+    bf16x8 w1f[4], w2f[4][2], w3f[2];
+    if constexpr (kTeam3) {
+      // read at each step: the empty asm keeps the loads in the loop
+      uint32_t wofs = 0;
+      asm volatile("" : "+v"(wofs));
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) {
+        w1f[mt] = wfrag[mt * 64 + lane + wofs];
+        w2f[mt][0] = wfrag[(4 + 2 * mt) * 64 + lane + wofs];
+        w2f[mt][1] = wfrag[(5 + 2 * mt) * 64 + lane + wofs];
+      }
+      w3f[0] = wfrag[12 * 64 + lane + wofs];
+      w3f[1] = wfrag[13 * 64 + lane + wofs];
+    } else {
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) {
+        w1f[mt] = rw1f[mt];
+        w2f[mt][0] = rw2f[mt][0];
+        w2f[mt][1] = rw2f[mt][1];
+      }
+      w3f[0] = rw3f[0];
+      w3f[1] = rw3f[1];
+    }
     floatx4 b1v[4], b2v[4];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
@@ -340,7 +419,7 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
       floatx4 lg = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3f[0], hc[0], b3f, 0, 0, 0);
       lg = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3f[1], hc[1], lg, 0, 0, 0);
       // lane (g, c16) holds logits 4g..4g+3 of robot n
-      logit_w[g * 64 + n] = make_float4(lg[0], lg[1], lg[2], lg[3]);
+      if (!kTeam3 || g < 2) logit_w[g * 64 + n] = make_float4(lg[0], lg[1], lg[2], lg[3]);
     }
     wave_lds_sync();
 
@@ -365,8 +444,8 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
       const int ph = t & 3;
       if (ph == 0) {
         const auto *P = K.get();
-        qblk = stream_block(P->key0, P->key1, env_id, A.t0 + (uint32_t)(t + (i & 3)), kPolicy,
-                            (uint32_t)(i >> 2), 0u);
+        qblk = stream_block(P->key0, P->key1, env_id, A.t0 + (uint32_t)(t + (il & 3)), kPolicy,
+                            (uint32_t)(il >> 2), 0u);
       }
       uint4 src;
       switch (ph) {
@@ -375,7 +454,7 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
         case 2: src = make_uint4(dpp<0xAA>((int)qblk.x), dpp<0xAA>((int)qblk.y), dpp<0xAA>((int)qblk.z), dpp<0xAA>((int)qblk.w)); break;
         default: src = make_uint4(dpp<0xFF>((int)qblk.x), dpp<0xFF>((int)qblk.y), dpp<0xFF>((int)qblk.z), dpp<0xFF>((int)qblk.w)); break;
       }
-      rbits = word(src, i & 3);
+      rbits = word(src, il & 3);
     } else {
       const auto *P = K.get();
       rbits = word(stream_block(P->key0, P->key1, env_id, A.t0 + (uint32_t)t, kPolicy,
@@ -400,7 +479,7 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
     pc.mark(kPhSample);
     // ---- 4. env step --------------------------------------------------------
     if (env_ok) {
-      const StepOut<float> so = env_step_group<float, G, PP>(K, A.C.qp_cap, sh, lane, i, N, on, env_id,
+      const StepOut<float> so = env_step_group<float, G, PP>(K, A.C.qp_cap, sh, lane, il, N, on, env_id,
                                                          A.t0 + (uint32_t)t, action, x, y, th, c, s, gx, gy, step,
                                                          episode, false,
 #ifdef RS_PHASE_TIMERS
@@ -409,7 +488,7 @@ __global__ __launch_bounds__(kRollBlock, 2) void k_rollout(RolloutArgs A) {
                                                          nullptr
 #endif
                                                          );
-      if (i == 0) {
+      if (il == 0) {
         (A.reward + (size_t)t * A.E)[(uint32_t)e] = so.reward;
         (A.done + (size_t)t * A.E)[(uint32_t)e] = so.done ? 1 : 0;
         if constexpr (STATS) qp_stats_add(A.qp_stats + (size_t)e * kQPStats, so.qp);
