@@ -254,6 +254,27 @@ rs_status env_step(rs_ctx *ctx, const rs_params *p, const rs_batch *b, const uin
                    uint8_t *infeasible, int32_t *qp_stats, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * env_steps -- `steps` consecutive env_step calls (Sec. 4.1, the step as
+ * above) of a uniform batch in one launch, the state held on chip between
+ * them: the persistent form of env_step in either precision (p->dtype), e.g.
+ * the 1000 steps of a single FP64 env. Step k (0-based) runs at stream time
+ * t_global0 + k with the actions env_step draws when given none (the
+ * discrete and waypoint controllers; go-to-goal takes none). Results are
+ * those of `steps` env_step calls with actions NULL at the same stream
+ * times, bit for bit. b is updated in place.
+ *  reward_out [steps][E] (float/double by dtype), done_out [steps][E] uint8:
+ *    per step, as env_step's reward and done; obs_final [E*N][2N+4]
+ *    (float/double): the observation of the final state; qp_stats
+ *    [E][RS_QPS_COUNT] int32, accumulated. Each may be NULL.
+ *  steps >= 0 (0: nothing is launched); steps * E must fit in int32.
+ *  Errors: RS_ERR_INVALID_ARG for a NULL ctx, invalid params or batch, or
+ *  steps out of range; RS_ERR_DEVICE if the launch fails.
+ * ------------------------------------------------------------------------- */
+rs_status env_steps(rs_ctx *ctx, const rs_params *p, const rs_batch *b, int32_t steps,
+                    int64_t t_global0, void *reward_out, uint8_t *done_out, void *obs_final,
+                    int32_t *qp_stats, void *stream);
+
+/* ---------------------------------------------------------------------------
  * barrier_certificate -- steps 1 (pre-clip) and 2 of env_step alone, for
  * E environments of N robots: given projection points (px, py) and nominal
  * commands (ux_nom, uy_nom) [E*N], writes the exact minimiser (ux, uy) [E*N].

@@ -1,7 +1,8 @@
 """Secondary benchmarks of the batched Robotarium step (one MI355X).
 
   single_env_f64   1 env x 4 robots, go-to-goal, FP64, 1000 steps: per-step
-                   env_step launches, plain and hipGraph-captured (us/step)
+                   env_step launches, plain and hipGraph-captured, and one
+                   persistent env_steps launch (us/step)
   uniform_4096x4   4096 envs x 4 robots, random moves, 1000 steps: per-step
                    env_step launches (plain, graph) and one persistent env_run
   uneven_8192      8192 envs, N in {2,4,6,8,12} (0.1/0.3/0.3/0.2/0.1), 1000
@@ -91,9 +92,17 @@ def single_env_f64(R, ctx, seed=0, steps=1000):
         g.replay()
     _sync()
     graph = (time.perf_counter() - t0) / steps * 1e6
+    R.env_steps(ctx, p, b, 10, t_global0=2 * steps)  # warm-up
+    _sync()
+    t0 = time.perf_counter()
+    R.env_steps(ctx, p, b, steps, t_global0=3 * steps)
+    _sync()
+    persistent = (time.perf_counter() - t0) / steps * 1e6
     return {"config": "single_env_f64", "envs": 1, "robots": 4, "steps": steps,
             "us_per_step_plain": plain, "us_per_step_graph": graph,
-            "robot_steps_per_s_graph": 4 / (graph * 1e-6)}
+            "us_per_step_persistent": persistent,
+            "robot_steps_per_s_graph": 4 / (graph * 1e-6),
+            "robot_steps_per_s_persistent": 4 / (persistent * 1e-6)}
 
 
 def uniform_4096x4(R, ctx, seed=0, steps=1000):

@@ -125,6 +125,68 @@ __global__ __launch_bounds__(kBlock) void k_env_step(StepArgs<T> A) {
 }
 
 // ---------------------------------------------------------------------------
+// env_steps: `steps` env steps of a uniform batch in one launch, the state in
+// registers between them (the persistent form of env_step, FP32 or FP64)
+// ---------------------------------------------------------------------------
+template <typename T> struct StepsArgs {
+  SimConst<T> C;
+  int E, N, steps;
+  uint32_t env_base;
+  uint32_t t0;
+  T *x, *y, *th, *gx, *gy;
+  int32_t *step, *episode;
+  T *reward;                     // [steps][E] (may be NULL)
+  uint8_t *done;                 // [steps][E] (may be NULL)
+  T *obs;                        // final state [E*N][2N+4] (may be NULL)
+  int32_t *qp_stats;             // [E][kQPStats] accumulated (may be NULL)
+  unsigned long long *qp_fail;   // the context's failure counters
+};
+
+template <typename T, int G, bool PP>
+__global__ __launch_bounds__(kBlock) void k_env_steps(StepsArgs<T> A) {
+  __shared__ QPScratch<T, G> qs[kBlock / G];
+  const int lane = threadIdx.x & 63;
+  const int i = threadIdx.x & (G - 1);
+  const int e = blockIdx.x * (kBlock / G) + threadIdx.x / G;
+  if (e >= A.E) return;  // whole group leaves together
+  const int N = A.N;
+  const bool on = i < N;
+  const size_t r = (size_t)e * N + (on ? i : 0);
+  T x = A.x[r], y = A.y[r], th = A.th[r], gx = A.gx[r], gy = A.gy[r];
+  int step = A.step[e], episode = A.episode[e];
+  const uint32_t env_id = A.env_base + (uint32_t)e;
+  const ConstRef<T> K = kernarg_const<T>(offsetof(StepsArgs<T>, C));
+  // complete the state loads before the loop: an in-loop wait on them would
+  // also wait for the loop's own stores
+  __builtin_amdgcn_s_waitcnt(0);
+  T s, c;
+  sincos_t(th, &s, &c);
+  for (int k = 0; k < A.steps; ++k) {
+    const uint32_t t = A.t0 + (uint32_t)k;
+    int action = 0;
+    if (A.C.controller != RS_CTRL_GOTO)
+      action = drawn_action(K.get()->key0, K.get()->key1, env_id, t, i);
+    const StepOut<T> out = env_step_group<T, G, PP>(K, A.C.qp_cap, &qs[threadIdx.x / G], lane, i,
+                                                    N, on, env_id, t, action, x, y, th, c, s, gx,
+                                                    gy, step, episode, false);
+    if (i == 0) {
+      if (A.reward) A.reward[(size_t)k * A.E + e] = out.reward;
+      if (A.done) A.done[(size_t)k * A.E + e] = out.done ? 1 : 0;
+      if (A.qp_stats) qp_stats_add(A.qp_stats + (size_t)e * kQPStats, out.qp);
+      qp_fail_count(A.qp_fail, out.qp);
+    }
+  }
+  if (on) {
+    A.x[r] = x; A.y[r] = y; A.th[r] = th; A.gx[r] = gx; A.gy[r] = gy;
+  }
+  if (A.obs) write_obs<T, G>(A.obs + r * (2 * N + 4), lane, i, N, on, x, y, c, s, gx, gy);
+  if (i == 0) {
+    A.step[e] = step;
+    A.episode[e] = episode;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // env_reset
 // ---------------------------------------------------------------------------
 template <typename T> struct ResetArgs {
@@ -299,6 +361,33 @@ static rs_status do_env_step(rs_ctx *ctx, const rs_params *p, const rs_batch *b,
 }
 
 template <typename T>
+static rs_status do_env_steps(rs_ctx *ctx, const rs_params *p, const rs_batch *b, int32_t steps,
+                              int64_t t_global0, void *reward, uint8_t *done, void *obs,
+                              int32_t *qp_stats, hipStream_t st) {
+  StepsArgs<T> A;
+  A.C = make_const<T>(*p);
+  A.E = b->num_envs;
+  A.N = b->robots;
+  A.steps = steps;
+  A.env_base = (uint32_t)b->env_id_base;
+  A.t0 = (uint32_t)t_global0;
+  A.x = (T *)b->x; A.y = (T *)b->y; A.th = (T *)b->theta; A.gx = (T *)b->goal_x; A.gy = (T *)b->goal_y;
+  A.step = b->step; A.episode = b->episode;
+  A.reward = (T *)reward; A.done = done; A.obs = (T *)obs;
+  A.qp_stats = qp_stats;
+  A.qp_fail = ctx->qp_fail;
+  const int G = pow2_group(A.N);
+  if (p->scenario == RS_SCN_PREDATOR_PREY) {
+    RS_DISPATCH_G(G, hipLaunchKernelGGL((k_env_steps<T, GG, true>), dim3(blocks_for<T>(A.E, GG)),
+                                        dim3(kBlock), 0, st, A));
+  } else {
+    RS_DISPATCH_G(G, hipLaunchKernelGGL((k_env_steps<T, GG, false>), dim3(blocks_for<T>(A.E, GG)),
+                                        dim3(kBlock), 0, st, A));
+  }
+  return launch_status("env_steps");
+}
+
+template <typename T>
 static rs_status do_env_reset(const rs_params *p, const rs_batch *b, const uint8_t *mask,
                               void *obs, hipStream_t st) {
   ResetArgs<T> A;
@@ -470,6 +559,25 @@ rs_status env_step(rs_ctx *ctx, const rs_params *p, const rs_batch *b, const uin
                                infeasible, qp_stats, st);
   return do_env_step<float>(ctx, p, b, actions, t_global, obs, reward, done, max_violation,
                             infeasible, qp_stats, st);
+}
+
+rs_status env_steps(rs_ctx *ctx, const rs_params *p, const rs_batch *b, int32_t steps,
+                    int64_t t_global0, void *reward_out, uint8_t *done_out, void *obs_final,
+                    int32_t *qp_stats, void *stream) {
+  RS_CHECK_ARG(ctx != nullptr, "ctx is NULL");
+  rs_status s = check_params(p);
+  if (s != RS_OK) return s;
+  s = check_batch(b, p->dtype, true);
+  if (s != RS_OK) return s;
+  RS_CHECK_ARG(steps >= 0, "steps must be >= 0 (got %d)", steps);
+  RS_CHECK_ARG((int64_t)steps * b->num_envs <= INT32_MAX, "steps x num_envs must fit in int32");
+  if (steps == 0) return RS_OK;
+  hipStream_t st = (hipStream_t)stream;
+  if (p->dtype == RS_F64)
+    return do_env_steps<double>(ctx, p, b, steps, t_global0, reward_out, done_out, obs_final,
+                                qp_stats, st);
+  return do_env_steps<float>(ctx, p, b, steps, t_global0, reward_out, done_out, obs_final,
+                             qp_stats, st);
 }
 
 rs_status env_reset(rs_ctx *ctx, const rs_params *p, const rs_batch *b, const uint8_t *mask,

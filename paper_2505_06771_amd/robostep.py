@@ -126,6 +126,7 @@ def lib():
         "rs_phase_cycles": (i32, [_VP, _VP, i32]),
         "env_step": (i32, [_VP, P(RsParams), P(RsBatch), _VP, i64, _VP, _VP, _VP, _VP, _VP, _VP,
                            _VP]),
+        "env_steps": (i32, [_VP, P(RsParams), P(RsBatch), i32, i64, _VP, _VP, _VP, _VP, _VP]),
         "barrier_certificate": (i32, [_VP, P(RsParams), i32, i32, _VP, _VP, _VP, _VP, _VP, _VP,
                                       _VP, _VP, _VP, _VP, _VP]),
         "rollout": (i32, [_VP, P(RsParams), P(RsBatch), P(RsPolicy), i32, i64, _VP, _VP, _VP,
@@ -280,6 +281,15 @@ def env_step(ctx: Context, p: RsParams, b: Batch, actions=None, t_global: int = 
     _check(lib().env_step(ctx.handle, ctypes.byref(p), ctypes.byref(cb), _ptr(actions), t_global,
                           _ptr(obs), _ptr(reward), _ptr(done), _ptr(max_violation),
                           _ptr(infeasible), _ptr(qp_stats), _stream(stream)))
+
+
+def env_steps(ctx: Context, p: RsParams, b: Batch, steps: int, t_global0: int = 0, reward=None,
+              done=None, obs_final=None, qp_stats=None, stream=None):
+    """`steps` env_step calls (actions drawn) in one launch; reward/done [steps][E]."""
+    cb = b.c()
+    _check(lib().env_steps(ctx.handle, ctypes.byref(p), ctypes.byref(cb), steps, t_global0,
+                           _ptr(reward), _ptr(done), _ptr(obs_final), _ptr(qp_stats),
+                           _stream(stream)))
 
 
 def barrier_certificate(ctx: Context, p: RsParams, num_envs: int, robots: int, px, py, ux_nom,
