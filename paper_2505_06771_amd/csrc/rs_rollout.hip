@@ -108,10 +108,15 @@ __device__ __forceinline__ int perm_hidden(int s, int g, int j) {
 // would leave a second, partial round. That needs at most 168 VGPRs and 53 KiB
 // of LDS per block: the policy weights stay in LDS and are read at each step's
 // MLP, the staging and logit areas are sized to what three robots use.
-template <int NC> constexpr int rollout_waves_per_simd() { return NC == 3 ? 3 : 2; }
+// 16-lane groups (9 to 16 robots) hold more state per lane than 256 VGPRs
+// take, so they run one wavefront per SIMD with the accumulation registers
+// as well.
+template <int G, int NC> constexpr int rollout_waves_per_simd() {
+  return NC == 3 ? 3 : (G == 16 ? 1 : 2);
+}
 
 template <int G, int NC, bool PP, bool STATS>
-__global__ __launch_bounds__(kRollBlock, rollout_waves_per_simd<NC>()) void k_rollout(RolloutArgs A) {
+__global__ __launch_bounds__(kRollBlock, (rollout_waves_per_simd<G, NC>())) void k_rollout(RolloutArgs A) {
   constexpr int EPW = 64 / G;
   constexpr bool kTeam3 = NC == 3;
   // staging floats per wavefront: 3-robot rows are 10 floats, and the MLP
