@@ -2,6 +2,7 @@
 
     python -m paper_2505_06771_amd.build --phase-timers   # librobostep_timers.so
     python -m paper_2505_06771_amd.phases [--launches 8] [--envs 16384] [--robots 8] [--horizon 128]
+    python -m paper_2505_06771_amd.phases --stages   # certificate stages, product library
 
 Runs the policy rollout of the benchmark (seeded synthetic weights, discrete
 moves, all envs reset together at the start) with the diagnostic library,
@@ -12,6 +13,12 @@ wavefronts' totals and the least-squares slope of a wavefront's total on its
 number of steps with an active-set loop solve (the cost of such a step);
 then one JSON line over all launches. The product library carries none of
 this code.
+
+With --stages it runs the same launches with the product library instead and
+its in-kernel certificate counters (the qp_stats output of the rollout, a
+separately compiled counting variant of the kernel): the share of env-steps
+whose command each stage of the certificate produced, and the active-set
+iterations per loop solve.
 """
 from __future__ import annotations
 
@@ -31,6 +38,7 @@ def main(argv=None):
     ap.add_argument("--robots", type=int, default=8)
     ap.add_argument("--horizon", type=int, default=128)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--stages", action="store_true")
     args = ap.parse_args(argv)
 
     import numpy as np
@@ -40,10 +48,11 @@ def main(argv=None):
     from paper_2505_06771_amd import robostep as R
     from paper_2505_06771_amd import synth
 
-    if not os.path.exists(B.LIB_TIMERS):
-        raise RuntimeError(f"{B.LIB_TIMERS} is missing: build it with "
-                           "python -m paper_2505_06771_amd.build --phase-timers")
-    R.use_library(B.LIB_TIMERS)
+    if not args.stages:
+        if not os.path.exists(B.LIB_TIMERS):
+            raise RuntimeError(f"{B.LIB_TIMERS} is missing: build it with "
+                               "python -m paper_2505_06771_amd.build --phase-timers")
+        R.use_library(B.LIB_TIMERS)
     assert torch.cuda.is_available(), "the phase timers need a GPU"
     E, n, H = args.envs, args.robots, args.horizon
     if not 2 <= n <= 14:
@@ -68,6 +77,8 @@ def main(argv=None):
     for k in range(args.warmup):
         R.rollout(ctx, p, b, pol, H, k * H, obs, act, rew, done)
     torch.cuda.synchronize()
+    if args.stages:
+        return stages(R, ctx, p, b, pol, obs, act, rew, done, args)
     allP, ms = [], []
     for k in range(args.launches):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -98,6 +109,46 @@ def main(argv=None):
         "wavefront_total_over_mean_p50_p90_p99_max": [round(float(x), 3) for x in q],
         "loop_solve_steps_per_wavefront_mean": round(float(P[:, 6].mean()), 2),
         "loop_solve_steps_per_wavefront_max": int(P[:, 6].max()),
+    }
+    print(json.dumps(summary), flush=True)
+    ctx.close()
+
+
+STAGES = ["box", "one_row", "two_rows", "shared_robot", "active_set", "general", "infeasible",
+          "capped"]
+
+
+def stages(R, ctx, p, b, pol, obs, act, rew, done, args):
+    """Certificate stage shares over the launches, from the in-kernel counters."""
+    import numpy as np
+    import torch
+
+    E, H = args.envs, args.horizon
+    qs = torch.zeros((E, R.QPS_COUNT), dtype=torch.int32, device="cuda")
+    per_launch = []
+    for k in range(args.launches):
+        qs.zero_()
+        R.rollout(ctx, p, b, pol, H, (args.warmup + k) * H, obs, act, rew, done, qp_stats=qs)
+        torch.cuda.synchronize()
+        q = qs.cpu().numpy().astype(np.int64)
+        per_launch.append(q)
+        tot = q[:, :8].sum()
+        loops = q[:, R.QPS_ACTIVE_SET].sum() + q[:, R.QPS_GENERAL].sum()
+        per_env = q[:, R.QPS_ACTIVE_SET] + q[:, R.QPS_GENERAL]
+        per_wave = per_env.reshape(-1, 64 // (1 << (args.robots - 1).bit_length())).sum(axis=1)
+        print(f"launch {k}: env-steps {tot} | " + " ".join(
+            f"{nm} {q[:, j].sum() / tot:.4%}" for j, nm in enumerate(STAGES))
+            + f" | loop solves {loops}, per env max {int(per_env.max())}"
+            + f", summed over the envs of a wavefront max {int(per_wave.max())}", flush=True)
+    Q = np.concatenate(per_launch)
+    tot = Q[:, :8].sum()
+    loops = Q[:, R.QPS_ACTIVE_SET].sum() + Q[:, R.QPS_GENERAL].sum()
+    summary = {
+        "envs": E, "robots": args.robots, "horizon": H, "launches": args.launches,
+        "warmup": args.warmup, "env_steps": int(tot),
+        "share": {nm: float(Q[:, j].sum() / tot) for j, nm in enumerate(STAGES)},
+        "loop_solves_per_launch": float(loops / args.launches),
+        "iterations_per_loop_solve": float(Q[:, R.QPS_ITERATIONS].sum() / max(loops, 1)),
     }
     print(json.dumps(summary), flush=True)
     ctx.close()
